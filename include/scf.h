@@ -1,0 +1,189 @@
+/*
+ * scf.h -- C ABI of the MI355X (gfx950) binary Shan-Chen capillary-filling library, libscf.so.
+ *
+ * The library advances the two-component pseudo-potential D2Q9 BGK lattice Boltzmann model of
+ * S. Chibbaro, "Capillary filling with pseudo-potential binary Lattice-Boltzmann model"
+ * (Sec. 2: eqs. lbe, feq1-feq3, forcing, forcingw; Sec. 3: the reservoir + capillary set-up of
+ * Fig. 1) on one GPU, and reports the quantities the paper follows in time: the centre-line
+ * interface position z(t), the precursor-film front and the per-component mass.
+ *
+ * Conventions shared by every call
+ *  - Status: every int-returning call returns SCF_OK (0) or a negative SCF_E* code; the text of
+ *    the last error of the calling thread is scf_last_error().
+ *  - Memory: host arrays passed in are read during the call only and stay owned by the caller.
+ *    Device memory is NOT allocated by the library: the caller passes one device workspace
+ *    (dev_ws, at least scf_*workspace_bytes() bytes, 256-byte aligned) that must stay alive and
+ *    untouched until the matching *_destroy.  The caller also passes the HIP stream (a
+ *    hipStream_t cast to void*, NULL = the default stream); all device work is enqueued on it.
+ *  - Geometry: a box nx x ny, periodic in x and y.  Rows y = 0 and y = ny-1 are solid for
+ *    x in [x0, x1) (the coated capillary, bounce-back walls); elsewhere those rows are fluid
+ *    (the reservoir).  Channel height H = ny - 2.  Liquid (component A) is expected to start
+ *    at x < x0; observables are reported relative to x0.
+ *  - Field arrays are row-major (ny rows of nx values, x fastest), FP64 on the host.  The
+ *    device state is FP32.
+ *  - Threading: one context per stream; distinct contexts are independent.  Calls on one
+ *    context must not overlap.
+ */
+#ifndef SCF_H
+#define SCF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    SCF_OK = 0,
+    SCF_EINVAL = -1,     /* bad argument: sizes, tau <= 1/2, NULL pointer, small workspace */
+    SCF_ENOMEM = -2,     /* host allocation failed */
+    SCF_EDEVICE = -3,    /* a HIP runtime call failed (message names it) */
+    SCF_EUNSTABLE = -4,  /* the state holds a non-finite or negative (< -1e-3) density */
+    SCF_ESTATE = -5      /* call not valid in the current state (e.g. checkpoint mismatch) */
+};
+
+/* Step variants (scf_set_variant). */
+enum {
+    SCF_VARIANT_FUSED = 0,     /* one kernel per step: pull, densities with an LDS halo, forces,
+                                  equilibrium, collision, store (144 B per node update) */
+    SCF_VARIANT_TWO_KERNEL = 1 /* density kernel, then pull + collide kernel reading the density
+                                  field back (232 B per node update) */
+};
+
+typedef struct {
+    int32_t nx, ny;    /* box size, nx >= 3, ny >= 3, nx < 2^20, ny < 2^20 */
+    int32_t x0, x1;    /* solid rows y = 0 and y = ny-1 for x in [x0, x1); x0 == x1: no walls */
+} scf_geometry;
+
+typedef struct {
+    double G;          /* inter-component coupling of eq. forcing with psi_k = n_k, written with the
+                          D2Q9 neighbour weights 1/9 (axis) and 1/36 (diagonal): the paper's
+                          g_{AB} = G/9 on axis links and g_{AB}/4 on diagonal links; G > 0 repels */
+    double gw[2];      /* wall couplings g_kw rho_w of eq. forcingw (same weights); < 0 attracts */
+    double tau[2];     /* relaxation times tau_A, tau_B of eq. lbe, each > 1/2 */
+    double alpha[2];   /* rest fractions alpha_k of eqs. feq1-feq3 (4/9: usual D2Q9), in [0, 1) */
+    double mass[2];    /* molecular masses m_k, rho_k = m_k n_k (1 on the standard path), > 0 */
+} scf_params;
+
+typedef struct {
+    int64_t t;            /* time step of the sample */
+    double mass[2];       /* sum over fluid nodes of n_A and n_B (FP64 sum of FP32 values) */
+    double z;             /* centre-line front: first downward zero crossing of n_A - n_B
+                             scanning from x0/2, linearly refined, minus x0; NaN if none */
+    double precursor;     /* mean of the two wall-row film fronts; NaN if either is absent */
+    double precursor_lo;  /* row y = 1: first crossing of n_A through n_A(x0/2, centre)/3 */
+    double precursor_hi;  /* row y = ny-2 */
+    int32_t flags;        /* bit0: n_A - n_B < 0 at the reservoir centre (reservoir exhausted);
+                             bit1: a non-finite density or one below -1e-3 at a fluid node */
+    int32_t reserved;
+} scf_obs;
+
+typedef struct scf_ctx scf_ctx;
+typedef struct scf_batch scf_batch;
+
+/* ---------------------------------------------------------------------------------------------
+ * Single channel.
+ * ------------------------------------------------------------------------------------------- */
+
+/* Device workspace needed for one channel: two FP32 population buffers (2 x 2 x 9 planes),
+ * a 2-plane density field, per-row partial sums and one observation record; each plane is
+ * ny rows of nx rounded up to 64 floats.  0 if the geometry is invalid. */
+size_t scf_workspace_bytes(const scf_geometry* geom);
+
+/* Create a context and set every population to the rest equilibrium of eqs. feq1-feq3,
+ * f_i = f_i^eq(n_k, u = 0) with n_k = rho_k / m_k (solid nodes ignored).  rhoA, rhoB: host
+ * FP64 ny*nx arrays, copied.  Synchronises the stream before returning.
+ * Errors: SCF_EINVAL (geometry, params, workspace), SCF_EDEVICE. */
+int scf_init(scf_ctx** out, const scf_geometry* geom, const scf_params* params,
+             const double* rhoA, const double* rhoB, void* dev_ws, size_t ws_bytes,
+             void* hip_stream);
+
+/* Advance nsteps >= 0 time steps of eq. lbe: densities, forces (eqs. forcing, forcingw),
+ * common velocity, shifted equilibrium, BGK collision, streaming with half-way bounce-back.
+ * Asynchronous on the stream; launches are replayed from a captured HIP graph when nsteps is
+ * large enough.  Errors: SCF_EINVAL, SCF_EDEVICE (launch failure). */
+int scf_step(scf_ctx* ctx, int64_t nsteps);
+
+/* Observables of the current state (see scf_obs).  Enqueues two small kernels, copies one
+ * record to the host and synchronises the stream.  Returns SCF_EUNSTABLE (with *out filled)
+ * when flags bit1 is set. */
+int scf_observe(scf_ctx* ctx, scf_obs* out);
+
+/* Host copies of the current densities n_A, n_B (ny*nx each, FP64, 0 on solid nodes).
+ * Synchronises the stream. */
+int scf_get_density(scf_ctx* ctx, double* nA, double* nB);
+
+/* Host copy of the current populations f[k][i][y][x] (2*9*ny*nx FP64, directions numbered as
+ * in Sec. 2: 0 rest, 1-4 axis at 0/90/180/270 deg, 5-8 diagonals at 45/135/225/315 deg; solid
+ * nodes 0).  Uses the idle population buffer as staging.  Synchronises the stream. */
+int scf_get_populations(scf_ctx* ctx, double* f);
+
+/* Select the step kernel (SCF_VARIANT_*).  Default SCF_VARIANT_FUSED. */
+int scf_set_variant(scf_ctx* ctx, int32_t variant);
+
+/* Tile shape of the fused kernel: block width bx in {64, 128, 256} nodes along x and chunk
+ * height cy >= 1 rows (cy >= ny: whole columns); graph_steps >= 0 steps per captured graph
+ * (0 disables graphs).  Invalidates captured graphs.  Errors: SCF_EINVAL. */
+int scf_set_tile(scf_ctx* ctx, int32_t bx, int32_t cy, int32_t graph_steps);
+
+/* Time the candidate tile shapes on the current workspace for `trial_steps` steps each and
+ * keep the fastest; the state is restored afterwards (the initial densities are re-applied
+ * only if the context has not stepped yet, otherwise the current state is saved to host and
+ * restored).  Writes the chosen bx, cy to *bx, *cy when non-NULL. */
+int scf_autotune(scf_ctx* ctx, int32_t trial_steps, int32_t* bx, int32_t* cy);
+
+/* Elapsed time step count of the context. */
+int64_t scf_time(const scf_ctx* ctx);
+
+/* Checkpoint: header (magic, version, geometry, params, t) and the FP32 post-collision
+ * buffer, written to / read from a file.  scf_load requires the same geometry.
+ * Errors: SCF_EINVAL (path), SCF_ESTATE (mismatch or bad file), SCF_EDEVICE. */
+int scf_save(scf_ctx* ctx, const char* path);
+int scf_load(scf_ctx* ctx, const char* path);
+
+/* Release the context (host objects and graphs only; the workspace stays the caller's). */
+void scf_destroy(scf_ctx* ctx);
+
+/* Thread-local text of the last error, never NULL. */
+const char* scf_last_error(void);
+
+/* ---------------------------------------------------------------------------------------------
+ * Batched: nchan independent channels advanced together, one launch per step over a packed
+ * tile list of all channels (the calibration sweep: uneven H, L, wall couplings and tau).
+ * ------------------------------------------------------------------------------------------- */
+
+/* Workspace for nchan channels with room for max_samples observation records per channel. */
+size_t scf_batch_workspace_bytes(int32_t nchan, const scf_geometry* geoms, int32_t max_samples);
+
+/* geoms, params, rhoA[c], rhoB[c]: arrays of nchan entries (host).  Every sample_every >= 1
+ * steps the observables of all channels are recorded on the device (up to max_samples each,
+ * including the t = 0 record).  Errors as scf_init. */
+int scf_batch_init(scf_batch** out, int32_t nchan, const scf_geometry* geoms,
+                   const scf_params* params, const double* const* rhoA, const double* const* rhoB,
+                   int32_t sample_every, int32_t max_samples, void* dev_ws, size_t ws_bytes,
+                   void* hip_stream);
+
+/* Advance every channel by nsteps, recording samples on the way.  Asynchronous. */
+int scf_batch_step(scf_batch* b, int64_t nsteps);
+
+/* Copy the recorded samples to out[c * max_samples + s] (nchan * max_samples records) and the
+ * number recorded per channel to *nsamples.  Synchronises the stream.  Returns SCF_EUNSTABLE
+ * if any recorded sample has flags bit1 set (all records are still written). */
+int scf_batch_observe(scf_batch* b, scf_obs* out, int64_t* nsamples);
+
+/* Host copy of channel c's densities (ny*nx FP64 each). */
+int scf_batch_get_density(scf_batch* b, int32_t c, double* nA, double* nB);
+
+/* Tile shape and graph length of the batched step, as scf_set_tile. */
+int scf_batch_set_tile(scf_batch* b, int32_t bx, int32_t cy, int32_t graph_steps);
+
+/* Autotune the batched step as scf_autotune (before the first scf_batch_step). */
+int scf_batch_autotune(scf_batch* b, int32_t trial_steps, int32_t* bx, int32_t* cy);
+
+void scf_batch_destroy(scf_batch* b);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SCF_H */

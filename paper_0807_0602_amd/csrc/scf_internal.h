@@ -1,0 +1,68 @@
+// Internal interface between the HIP kernels (scf_kernels.hip) and the host runtime
+// (scf_runtime.hip) of libscf.  Not installed; the public ABI is include/scf.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace scf {
+
+// Per-channel constants, one table entry per channel, read by every kernel.
+// Device region of a channel, in floats from the workspace base:
+//   off + b*18*plane     population buffer b in {0,1}: [k][i][y][pitch], k = A,B; i = 0..8
+//   off + 36*plane       density field [k][y][pitch]
+struct Chan {
+    int32_t nx, ny, pitch, x0, x1, xs;   // xs = x0/2: liquid-reservoir centre (scan start)
+    int32_t row_base;                    // first entry of this channel in the packed row list
+    int32_t pad0;
+    int64_t off;                         // float offset of population buffer 0
+    int64_t plane;                       // ny * pitch
+    float G;                             // bulk coupling (D2Q9 weights)
+    float gw[2];                         // wall couplings
+    float omega[2];                      // 1/tau_k
+    float tm[2];                         // tau_k / m_k
+    float wm[2];                         // m_k / tau_k
+    float c1[2];                         // (1 - alpha_k) / 5: axis rest coefficient
+    float c0[2];                         // alpha_k: rest-direction coefficient (used at init)
+    float inv_m[2];                      // 1 / m_k
+    float pad1;
+};
+
+// One row of one channel, for the per-row kernels (two-kernel step, observe, init, copies).
+struct RowRef {
+    int32_t chan, y;
+};
+
+// Per-row partial sums written by the observe pass.
+struct RowPartial {
+    double mass[2];
+    int32_t bad;
+    int32_t pad[3];
+};
+
+// Observation record (layout of scf_obs in include/scf.h).
+struct ObsRec {
+    int64_t t;
+    double mass[2];
+    double z, precursor, precursor_lo, precursor_hi;
+    int32_t flags;
+    int32_t reserved;
+};
+
+struct TileDesc {
+    int32_t chan, xb, yb, ye;   // strip [xb, xb+bx) x rows [yb, ye)
+};
+
+// Kernel launchers (all asynchronous on `stream`; return hipSuccess or the launch error).
+hipError_t launch_init(const Chan* chans, const RowRef* rows, int nrows, float* ws, hipStream_t s);
+hipError_t launch_step_fused(int bx, const Chan* chans, const TileDesc* tiles, int ntiles,
+                             int grid, float* ws, int src, hipStream_t s);
+hipError_t launch_step_two_kernel(const Chan* chans, const RowRef* rows, int nrows, float* ws,
+                                  int src, hipStream_t s);
+hipError_t launch_observe(const Chan* chans, const RowRef* rows, int nrows, int nchan, float* ws,
+                          int src, RowPartial* partials, ObsRec* now, ObsRec* ring,
+                          int32_t* counter, int max_samples, int record, hipStream_t s);
+hipError_t launch_pull_out(const Chan* chans, const RowRef* rows, int nrows, float* ws, int src,
+                           hipStream_t s);
+
+}  // namespace scf

@@ -1,0 +1,557 @@
+// HIP kernels for gfx950 of the binary Shan-Chen capillary-filling step.
+//
+// Model (S. Chibbaro, "Capillary filling with pseudo-potential binary Lattice-Boltzmann
+// model", Sec. 2): per component k in {A, B} a D2Q9 BGK equation (eq. lbe) whose equilibrium
+// (eqs. feq1-feq3) is evaluated at a shifted velocity u_k^eq = U + tau_k F_k / rho_k, with the
+// common velocity U = sum_k (rho_k u_k / tau_k) / sum_k (rho_k / tau_k), the bulk
+// pseudo-potential force of eq. forcing (psi = n, cross-component coupling only) and the wall
+// force of eq. forcingw.  Walls are solid rows with half-way bounce-back (Sec. 3, Fig. 1).
+//
+// Storage: FP32, structure of arrays per component and direction, rows padded to 64 floats.
+// The resident buffer holds POST-COLLISION populations f*(t-1); a step pulls
+// f_i(x, t) = f*_i(x - c_i, t-1) (or the node's own opposite population when x - c_i is solid),
+// forms n_k(x, t), computes forces from the neighbours' n_k(t), collides and stores f*(t).
+//
+// Direction numbering of Sec. 2:
+//   i :  0  1  2  3  4  5  6  7  8
+//   cx:  0  1  0 -1  0  1 -1 -1  1
+//   cy:  0  0  1  0 -1  1  1 -1 -1
+#include "scf_internal.h"
+
+namespace scf {
+namespace {
+
+constexpr float W1 = 1.0f / 9.0f;    // interaction weight of axis links
+constexpr float W2 = 1.0f / 36.0f;   // interaction weight of diagonal links
+constexpr int kRowThreads = 256;     // block size of the per-row kernels
+
+__device__ __forceinline__ bool solid_at(const Chan& c, int x, int y) {
+    return (y == 0 || y == c.ny - 1) && (unsigned)(x - c.x0) < (unsigned)(c.x1 - c.x0);
+}
+__device__ __forceinline__ int dec_wrap(int v, int n) { return v == 0 ? n - 1 : v - 1; }
+__device__ __forceinline__ int inc_wrap(int v, int n) { return v == n - 1 ? 0 : v + 1; }
+
+// Rows 0, 1, ny-2, ny-1 may touch a solid node; all others never do.
+__device__ __forceinline__ bool near_wall(const Chan& c, int y) {
+    return c.x1 > c.x0 && (y <= 1 || y >= c.ny - 2);
+}
+
+// Pull the 18 populations streaming into node (x, y) from post-collision buffer g.
+template <bool WALLS>
+__device__ __forceinline__ void pull18(const float* __restrict__ g, const Chan& c, int x, int y,
+                                       float f[18]) {
+    const int xm = dec_wrap(x, c.nx), xp = inc_wrap(x, c.nx);
+    const int ym = dec_wrap(y, c.ny), yp = inc_wrap(y, c.ny);
+    const int64_t P = c.plane;
+    const int sx[9] = {x, xm, x, xp, x, xm, xp, xp, xm};
+    const int sy[9] = {y, y, ym, y, yp, ym, ym, yp, yp};
+    const int opp[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        int pi = i;
+        int idx = sy[i] * c.pitch + sx[i];
+        if (WALLS && i > 0 && solid_at(c, sx[i], sy[i])) {
+            pi = opp[i];
+            idx = y * c.pitch + x;
+        }
+        f[i] = g[pi * P + idx];
+        f[9 + i] = g[(9 + pi) * P + idx];
+    }
+}
+
+__device__ __forceinline__ void pull_node(const float* __restrict__ g, const Chan& c, int x, int y,
+                                          float f[18]) {
+    if (near_wall(c, y))
+        pull18<true>(g, c, x, y, f);
+    else
+        pull18<false>(g, c, x, y, f);
+}
+
+__device__ __forceinline__ float sum9(const float* f) {
+    float s = f[0];
+#pragma unroll
+    for (int i = 1; i < 9; ++i) s += f[i];
+    return s;
+}
+
+// sum_i w_i s(x + c_i) c_i over solid neighbours (eq. forcingw without -n_k G_kw).
+__device__ __forceinline__ void wall_sum(const Chan& c, int x, int y, float& sx, float& sy) {
+    const int xm = dec_wrap(x, c.nx), xp = inc_wrap(x, c.nx);
+    const int ym = dec_wrap(y, c.ny), yp = inc_wrap(y, c.ny);
+    const float sE = solid_at(c, xp, y), sW = solid_at(c, xm, y);
+    const float sN = solid_at(c, x, yp), sS = solid_at(c, x, ym);
+    const float sNE = solid_at(c, xp, yp), sNW = solid_at(c, xm, yp);
+    const float sSW = solid_at(c, xm, ym), sSE = solid_at(c, xp, ym);
+    sx = W1 * (sE - sW) + W2 * ((sNE - sSW) + (sSE - sNW));
+    sy = W1 * (sN - sS) + W2 * ((sNE - sSW) + (sNW - sSE));
+}
+
+// Equilibrium of eqs. feq1-feq3 at (n, u) and BGK relaxation of one component's 9 populations,
+// f*_i = f_i + omega D_i with D_i = f_i^eq - f_i.  For i > 0 the equilibrium is the rest part
+// r_i = n (1 - alpha)/5 (axis) or a quarter of it (diagonal) plus n times (or n/4 times)
+//   c.u/3 + (c.u)^2/2 - u.u/6,
+// and D_i is formed as (r_i - f_i) + n dev_i so that only small numbers are rounded; the rest
+// direction takes D_0 = -sum_{i>0} D_i, which keeps the node's mass to the rounding of small
+// terms.  The odd part c.u/3 uses a two-term 1/3: a single rounded 1/3 would scale the
+// equilibrium momentum by (1 + 3e-8) at every collision, a bias that compounds over steps.
+constexpr float kThirdHi = 1.0f / 3.0f;
+constexpr float kThirdLo = (float)(1.0 / 3.0 - (double)kThirdHi);
+
+__device__ __forceinline__ float third(float v) { return __builtin_fmaf(v, kThirdHi, v * kThirdLo); }
+
+__device__ __forceinline__ void relax_store(const float* f, float n, float ux, float uy, float c1,
+                                            float om, float* __restrict__ out, int64_t P, int idx) {
+    const float usq6 = (ux * ux + uy * uy) * (1.0f / 6.0f);
+    const float up = ux + uy, um = uy - ux;
+    const float ox = third(ux), oy = third(uy), op = third(up), oq = third(um);
+    const float ex = 0.5f * ux * ux - usq6, ey = 0.5f * uy * uy - usq6;
+    const float ep = 0.5f * up * up - usq6, eq = 0.5f * um * um - usq6;
+    const float r = n * c1, r4 = 0.25f * r, n4 = 0.25f * n;
+    float D[9];
+    D[1] = (r - f[1]) + n * (ex + ox);
+    D[3] = (r - f[3]) + n * (ex - ox);
+    D[2] = (r - f[2]) + n * (ey + oy);
+    D[4] = (r - f[4]) + n * (ey - oy);
+    D[5] = (r4 - f[5]) + n4 * (ep + op);
+    D[7] = (r4 - f[7]) + n4 * (ep - op);
+    D[6] = (r4 - f[6]) + n4 * (eq + oq);
+    D[8] = (r4 - f[8]) + n4 * (eq - oq);
+    D[0] = -(((D[1] + D[2]) + (D[3] + D[4])) + ((D[5] + D[6]) + (D[7] + D[8])));
+#pragma unroll
+    for (int i = 0; i < 9; ++i) out[i * P + idx] = f[i] + om * D[i];
+}
+
+// Collide one fluid node: f holds its pulled populations (A then B), nA/nB their sums,
+// sAx.. the weighted neighbour sums of n_A and n_B, swx/swy the weighted solid-neighbour sum.
+__device__ __forceinline__ void collide_store(const Chan& c, const float f[18], float nA, float nB,
+                                              float sAx, float sAy, float sBx, float sBy, float swx,
+                                              float swy, float* __restrict__ d, int idx) {
+    const float jAx = (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
+    const float jAy = (f[2] - f[4]) + (f[5] - f[7]) + (f[6] - f[8]);
+    const float jBx = (f[10] - f[12]) + (f[14] - f[15]) + (f[17] - f[16]);
+    const float jBy = (f[11] - f[13]) + (f[14] - f[16]) + (f[15] - f[17]);
+    // a_k = F_k / n_k: -G sum w n_kbar(x+c) c  -  G_kw sum w s(x+c) c
+    const float aAx = -c.G * sBx - c.gw[0] * swx, aAy = -c.G * sBy - c.gw[0] * swy;
+    const float aBx = -c.G * sAx - c.gw[1] * swx, aBy = -c.G * sAy - c.gw[1] * swy;
+    const float den = c.wm[0] * nA + c.wm[1] * nB;
+    const float Ux = (c.wm[0] * jAx + c.wm[1] * jBx) / den;
+    const float Uy = (c.wm[0] * jAy + c.wm[1] * jBy) / den;
+    const int64_t P = c.plane;
+    relax_store(f, nA, Ux + c.tm[0] * aAx, Uy + c.tm[0] * aAy, c.c1[0], c.omega[0], d, P, idx);
+    relax_store(f + 9, nB, Ux + c.tm[1] * aBx, Uy + c.tm[1] * aBy, c.c1[1], c.omega[1], d + 9 * P, P,
+                idx);
+}
+
+// ---------------------------------------------------------------------------------------------
+// Fused step.  A block of BX threads owns a strip of BX columns and a chunk [yb, ye) of rows,
+// walked bottom to top.  Iteration `it` pulls row yb-1+it, writes its densities into a 4-slot
+// LDS ring (plus the two halo columns, pulled by lanes 0 and 1), and after one barrier collides
+// the row below it, whose populations were kept in registers from the previous iteration.
+// Rows yb-1 and ye are density-only halos.  A slot written at iteration it+1 was last read by
+// the collision of iteration it-1, which every thread finished before the barrier of iteration
+// it, so one barrier per row suffices.
+// ---------------------------------------------------------------------------------------------
+template <int BX>
+__global__ void __launch_bounds__(BX)
+k_step_fused(const Chan* __restrict__ chans, const TileDesc* __restrict__ tiles, int ntiles,
+             int vtotal, float* __restrict__ ws, int src) {
+    __shared__ float sn[2][4][BX + 2];
+    const int tid = threadIdx.x;
+    const int per = vtotal >> 3;
+    for (int v = blockIdx.x; v < vtotal; v += gridDim.x) {
+        // consecutive tiles of the list go to the same XCD (blocks are dealt round-robin to 8)
+        const int t = (v & 7) * per + (v >> 3);
+        if (t >= ntiles) continue;
+        const TileDesc td = tiles[t];
+        const Chan c = chans[td.chan];
+        const int w = min(BX, c.nx - td.xb);
+        const bool act = tid < w;
+        const int x = td.xb + (act ? tid : w - 1);
+        const float* __restrict__ g = ws + c.off + (int64_t)src * 18 * c.plane;
+        float* __restrict__ d = ws + c.off + (int64_t)(src ^ 1) * 18 * c.plane;
+        const bool walls = c.x1 > c.x0;
+        const int hx = tid == 0 ? (td.xb == 0 ? c.nx - 1 : td.xb - 1)
+                                : (td.xb + w == c.nx ? 0 : td.xb + w);
+        const int hslot = tid == 0 ? 0 : w + 1;
+        float q[18];
+#pragma unroll
+        for (int i = 0; i < 18; ++i) q[i] = 0.0f;
+        float qA = 0.0f, qB = 0.0f;
+        int y = td.yb == 0 ? c.ny - 1 : td.yb - 1;
+        const int niter = td.ye - td.yb + 2;
+        for (int it = 0; it < niter; ++it) {
+            const int slot = it & 3;
+            float p[18];
+            pull_node(g, c, x, y, p);
+            float nA = 0.0f, nB = 0.0f;
+            if (!(walls && solid_at(c, x, y))) {
+                nA = sum9(p);
+                nB = sum9(p + 9);
+            }
+            if (act) {
+                sn[0][slot][tid + 1] = nA;
+                sn[1][slot][tid + 1] = nB;
+            }
+            if (tid < 2) {
+                float h[18];
+                pull_node(g, c, hx, y, h);
+                float hA = 0.0f, hB = 0.0f;
+                if (!(walls && solid_at(c, hx, y))) {
+                    hA = sum9(h);
+                    hB = sum9(h + 9);
+                }
+                sn[0][slot][hslot] = hA;
+                sn[1][slot][hslot] = hB;
+            }
+            __syncthreads();
+            if (it >= 2 && act) {
+                const int yc = y == 0 ? c.ny - 1 : y - 1;
+                if (!(walls && solid_at(c, x, yc))) {
+                    const int sm = (it - 2) & 3, s0 = (it - 1) & 3, sp = slot;
+                    const int l = tid + 1;
+                    const float AE = sn[0][s0][l + 1], AW = sn[0][s0][l - 1];
+                    const float AN = sn[0][sp][l], AS = sn[0][sm][l];
+                    const float ANE = sn[0][sp][l + 1], ANW = sn[0][sp][l - 1];
+                    const float ASW = sn[0][sm][l - 1], ASE = sn[0][sm][l + 1];
+                    const float BE = sn[1][s0][l + 1], BW = sn[1][s0][l - 1];
+                    const float BN = sn[1][sp][l], BS = sn[1][sm][l];
+                    const float BNE = sn[1][sp][l + 1], BNW = sn[1][sp][l - 1];
+                    const float BSW = sn[1][sm][l - 1], BSE = sn[1][sm][l + 1];
+                    const float sAx = W1 * (AE - AW) + W2 * ((ANE - ASW) + (ASE - ANW));
+                    const float sAy = W1 * (AN - AS) + W2 * ((ANE - ASW) + (ANW - ASE));
+                    const float sBx = W1 * (BE - BW) + W2 * ((BNE - BSW) + (BSE - BNW));
+                    const float sBy = W1 * (BN - BS) + W2 * ((BNE - BSW) + (BNW - BSE));
+                    float swx = 0.0f, swy = 0.0f;
+                    if (near_wall(c, yc)) wall_sum(c, x, yc, swx, swy);
+                    collide_store(c, q, qA, qB, sAx, sAy, sBx, sBy, swx, swy, d, yc * c.pitch + x);
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < 18; ++i) q[i] = p[i];
+            qA = nA;
+            qB = nB;
+            y = y == c.ny - 1 ? 0 : y + 1;
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------------------------
+// Two-kernel step: (1) densities of every node into the density field, (2) pull, neighbour
+// densities read back from the field, collision.  Same per-node arithmetic as the fused step.
+// One block per row; threads stride along x.
+// ---------------------------------------------------------------------------------------------
+__global__ void __launch_bounds__(kRowThreads)
+k_density(const Chan* __restrict__ chans, const RowRef* __restrict__ rows, float* __restrict__ ws,
+          int src) {
+    const RowRef r = rows[blockIdx.x];
+    const Chan c = chans[r.chan];
+    const float* __restrict__ g = ws + c.off + (int64_t)src * 18 * c.plane;
+    float* __restrict__ dn = ws + c.off + 36 * c.plane;
+    const bool walls = c.x1 > c.x0;
+    for (int x = threadIdx.x; x < c.nx; x += kRowThreads) {
+        float p[18];
+        pull_node(g, c, x, r.y, p);
+        float nA = 0.0f, nB = 0.0f;
+        if (!(walls && solid_at(c, x, r.y))) {
+            nA = sum9(p);
+            nB = sum9(p + 9);
+        }
+        dn[r.y * c.pitch + x] = nA;
+        dn[c.plane + r.y * c.pitch + x] = nB;
+    }
+}
+
+__global__ void __launch_bounds__(kRowThreads)
+k_collide(const Chan* __restrict__ chans, const RowRef* __restrict__ rows, float* __restrict__ ws,
+          int src) {
+    const RowRef r = rows[blockIdx.x];
+    const Chan c = chans[r.chan];
+    const float* __restrict__ g = ws + c.off + (int64_t)src * 18 * c.plane;
+    float* __restrict__ d = ws + c.off + (int64_t)(src ^ 1) * 18 * c.plane;
+    const float* __restrict__ nA_f = ws + c.off + 36 * c.plane;
+    const float* __restrict__ nB_f = nA_f + c.plane;
+    const bool walls = c.x1 > c.x0;
+    const int y = r.y;
+    if (walls && (y == 0 || y == c.ny - 1) && c.x0 == 0 && c.x1 == c.nx) return;
+    const int ym = dec_wrap(y, c.ny), yp = inc_wrap(y, c.ny);
+    for (int x = threadIdx.x; x < c.nx; x += kRowThreads) {
+        if (walls && solid_at(c, x, y)) continue;
+        float p[18];
+        pull_node(g, c, x, y, p);
+        const float nA = sum9(p), nB = sum9(p + 9);
+        const int xm = dec_wrap(x, c.nx), xp = inc_wrap(x, c.nx);
+        const int r0 = y * c.pitch, rm = ym * c.pitch, rp = yp * c.pitch;
+        const float AE = nA_f[r0 + xp], AW = nA_f[r0 + xm], AN = nA_f[rp + x], AS = nA_f[rm + x];
+        const float ANE = nA_f[rp + xp], ANW = nA_f[rp + xm], ASW = nA_f[rm + xm], ASE = nA_f[rm + xp];
+        const float BE = nB_f[r0 + xp], BW = nB_f[r0 + xm], BN = nB_f[rp + x], BS = nB_f[rm + x];
+        const float BNE = nB_f[rp + xp], BNW = nB_f[rp + xm], BSW = nB_f[rm + xm], BSE = nB_f[rm + xp];
+        const float sAx = W1 * (AE - AW) + W2 * ((ANE - ASW) + (ASE - ANW));
+        const float sAy = W1 * (AN - AS) + W2 * ((ANE - ASW) + (ANW - ASE));
+        const float sBx = W1 * (BE - BW) + W2 * ((BNE - BSW) + (BSE - BNW));
+        const float sBy = W1 * (BN - BS) + W2 * ((BNE - BSW) + (BNW - BSE));
+        float swx = 0.0f, swy = 0.0f;
+        if (near_wall(c, y)) wall_sum(c, x, y, swx, swy);
+        collide_store(c, p, nA, nB, sAx, sAy, sBx, sBy, swx, swy, d, r0 + x);
+    }
+}
+
+// ---------------------------------------------------------------------------------------------
+// Initial state.  The resident buffer holds post-collision values, so it is set to the
+// populations that one pull turns into the rest equilibrium f_i = e_i n0(x) (e_0 = alpha,
+// e_axis = (1-alpha)/5, e_diag = (1-alpha)/20): g_i(x) = e_i n0(x + c_i) if x + c_i is fluid,
+// else e_i n0(x).  The FP64 host fields (rho_k, ny*nx) are staged in population buffer 1.
+// ---------------------------------------------------------------------------------------------
+__global__ void __launch_bounds__(kRowThreads)
+k_init(const Chan* __restrict__ chans, const RowRef* __restrict__ rows, float* __restrict__ ws) {
+    const RowRef r = rows[blockIdx.x];
+    const Chan c = chans[r.chan];
+    const double* __restrict__ rho = reinterpret_cast<const double*>(ws + c.off + 18 * c.plane);
+    float* __restrict__ g = ws + c.off;
+    const int64_t P = c.plane;
+    const int64_t cells = (int64_t)c.nx * c.ny;
+    const int y = r.y;
+    const int ym = dec_wrap(y, c.ny), yp = inc_wrap(y, c.ny);
+    for (int x = threadIdx.x; x < c.nx; x += kRowThreads) {
+        const int xm = dec_wrap(x, c.nx), xp = inc_wrap(x, c.nx);
+        const int nxs[9] = {x, xp, x, xm, x, xp, xm, xm, xp};   // x + c_i
+        const int nys[9] = {y, y, yp, y, ym, yp, yp, ym, ym};
+        const bool solid = solid_at(c, x, y);
+        const int idx = y * c.pitch + x;
+        for (int k = 0; k < 2; ++k) {
+            const double* rk = rho + k * cells;
+            const double n0 = rk[(int64_t)y * c.nx + x] * (double)c.inv_m[k];
+#pragma unroll
+            for (int i = 0; i < 9; ++i) {
+                const float e = i == 0 ? c.c0[k] : (i < 5 ? c.c1[k] : 0.25f * c.c1[k]);
+                double nn = n0;
+                if (!solid_at(c, nxs[i], nys[i]))
+                    nn = rk[(int64_t)nys[i] * c.nx + nxs[i]] * (double)c.inv_m[k];
+                g[(k * 9 + i) * P + idx] = solid ? 0.0f : e * (float)nn;
+            }
+        }
+    }
+}
+
+// Pulled populations f(t) of every node into buffer `1 - src`, layout [k][i][y][pitch].
+__global__ void __launch_bounds__(kRowThreads)
+k_pull_out(const Chan* __restrict__ chans, const RowRef* __restrict__ rows, float* __restrict__ ws,
+           int src) {
+    const RowRef r = rows[blockIdx.x];
+    const Chan c = chans[r.chan];
+    const float* __restrict__ g = ws + c.off + (int64_t)src * 18 * c.plane;
+    float* __restrict__ o = ws + c.off + (int64_t)(src ^ 1) * 18 * c.plane;
+    for (int x = threadIdx.x; x < c.nx; x += kRowThreads) {
+        float p[18];
+        pull_node(g, c, x, r.y, p);
+        const bool solid = solid_at(c, x, r.y);
+#pragma unroll
+        for (int i = 0; i < 18; ++i) o[i * c.plane + r.y * c.pitch + x] = solid ? 0.0f : p[i];
+    }
+}
+
+// ---------------------------------------------------------------------------------------------
+// Observables.  Pass 1 (one block per row): densities of the row into the density field,
+// FP64 row sums of n_A and n_B over fluid nodes and a health flag.  Pass 2 (one block per
+// channel): the row sums in fixed order, then the centre-line front and the wall-row film
+// fronts by a parallel first-crossing search.  Both passes are deterministic.
+// ---------------------------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ T block_sum(T v, T* scratch) {
+    const int tid = threadIdx.x;
+    scratch[tid] = v;
+    __syncthreads();
+    for (int s = kRowThreads / 2; s > 0; s >>= 1) {
+        if (tid < s) scratch[tid] += scratch[tid + s];
+        __syncthreads();
+    }
+    const T r = scratch[0];
+    __syncthreads();
+    return r;
+}
+
+__device__ __forceinline__ int block_min(int v, int* scratch) {
+    const int tid = threadIdx.x;
+    scratch[tid] = v;
+    __syncthreads();
+    for (int s = kRowThreads / 2; s > 0; s >>= 1) {
+        if (tid < s) scratch[tid] = min(scratch[tid], scratch[tid + s]);
+        __syncthreads();
+    }
+    const int r = scratch[0];
+    __syncthreads();
+    return r;
+}
+
+__global__ void __launch_bounds__(kRowThreads)
+k_obs_rows(const Chan* __restrict__ chans, const RowRef* __restrict__ rows, float* __restrict__ ws,
+           int src, RowPartial* __restrict__ part) {
+    __shared__ double sd[kRowThreads];
+    __shared__ int si[kRowThreads];
+    const RowRef r = rows[blockIdx.x];
+    const Chan c = chans[r.chan];
+    const float* __restrict__ g = ws + c.off + (int64_t)src * 18 * c.plane;
+    float* __restrict__ dn = ws + c.off + 36 * c.plane;
+    double mA = 0.0, mB = 0.0;
+    int bad = 0;
+    for (int x = threadIdx.x; x < c.nx; x += kRowThreads) {
+        float p[18];
+        pull_node(g, c, x, r.y, p);
+        float nA = 0.0f, nB = 0.0f;
+        if (!solid_at(c, x, r.y)) {
+            nA = sum9(p);
+            nB = sum9(p + 9);
+            mA += (double)nA;
+            mB += (double)nB;
+            if (!(nA >= -1e-3f) || !(nB >= -1e-3f) || !isfinite(nA) || !isfinite(nB)) bad = 1;
+        }
+        dn[r.y * c.pitch + x] = nA;
+        dn[c.plane + r.y * c.pitch + x] = nB;
+    }
+    mA = block_sum(mA, sd);
+    mB = block_sum(mB, sd);
+    bad = block_sum(bad, si);
+    if (threadIdx.x == 0) {
+        RowPartial o;
+        o.mass[0] = mA;
+        o.mass[1] = mB;
+        o.bad = bad;
+        o.pad[0] = o.pad[1] = o.pad[2] = 0;
+        part[c.row_base + r.y] = o;
+    }
+}
+
+// Linear refinement of a first downward crossing at x (v(x) >= level > v(x+1)), minus x0.
+__device__ __forceinline__ double refine(double vx, double vx1, int x, double level, int x0) {
+    return (double)x + (vx - level) / (vx - vx1) - (double)x0;
+}
+
+__global__ void __launch_bounds__(kRowThreads)
+k_obs_final(const Chan* __restrict__ chans, const float* __restrict__ ws,
+            const RowPartial* __restrict__ part, ObsRec* __restrict__ now, ObsRec* __restrict__ ring,
+            const int32_t* __restrict__ counter, int max_samples, int record) {
+    __shared__ double sd[kRowThreads];
+    __shared__ int si[kRowThreads];
+    const int ch = blockIdx.x;
+    const Chan c = chans[ch];
+    const int tid = threadIdx.x;
+    const float* __restrict__ nA = ws + c.off + 36 * c.plane;
+    const float* __restrict__ nB = nA + c.plane;
+    double mA = 0.0, mB = 0.0;
+    int bad = 0;
+    for (int y = tid; y < c.ny; y += kRowThreads) {
+        const RowPartial p = part[c.row_base + y];
+        mA += p.mass[0];
+        mB += p.mass[1];
+        bad |= p.bad;
+    }
+    mA = block_sum(mA, sd);
+    mB = block_sum(mB, sd);
+    bad = block_sum(bad, si);
+    // centre line: rows ny/2-1 and ny/2 averaged (ny even) or row (ny-1)/2
+    const bool even = (c.ny & 1) == 0;
+    const int ra = even ? c.ny / 2 - 1 : (c.ny - 1) / 2;
+    const int rb = even ? c.ny / 2 : ra;
+    auto centre = [&](const float* f, int x) -> double {
+        return even ? 0.5 * ((double)f[ra * c.pitch + x] + (double)f[rb * c.pitch + x])
+                    : (double)f[ra * c.pitch + x];
+    };
+    auto phi = [&](int x) -> double { return centre(nA, x) - centre(nB, x); };
+    const int big = 0x7fffffff;
+    int xz = big;
+    for (int x = c.xs + tid; x + 1 < c.nx; x += kRowThreads)
+        if (xz == big && phi(x) >= 0.0 && phi(x + 1) < 0.0) xz = x;
+    xz = block_min(xz, si);
+    const double level = centre(nA, c.xs) / 3.0;
+    const float* rowlo = nA + 1 * c.pitch;
+    const float* rowhi = nA + (c.ny - 2) * c.pitch;
+    int xlo = big, xhi = big;
+    for (int x = c.xs + tid; x + 1 < c.nx; x += kRowThreads) {
+        if (xlo == big && (double)rowlo[x] >= level && (double)rowlo[x + 1] < level) xlo = x;
+        if (xhi == big && (double)rowhi[x] >= level && (double)rowhi[x + 1] < level) xhi = x;
+    }
+    xlo = block_min(xlo, si);
+    xhi = block_min(xhi, si);
+    if (tid == 0) {
+        ObsRec o;
+        o.t = 0;
+        o.mass[0] = mA;
+        o.mass[1] = mB;
+        o.z = xz == big ? __builtin_nan("") : refine(phi(xz), phi(xz + 1), xz, 0.0, c.x0);
+        o.precursor_lo = xlo == big ? __builtin_nan("")
+                                    : refine(rowlo[xlo], rowlo[xlo + 1], xlo, level, c.x0);
+        o.precursor_hi = xhi == big ? __builtin_nan("")
+                                    : refine(rowhi[xhi], rowhi[xhi + 1], xhi, level, c.x0);
+        o.precursor = 0.5 * (o.precursor_lo + o.precursor_hi);
+        o.flags = (phi(c.xs) < 0.0 ? 1 : 0) | (bad ? 2 : 0);
+        o.reserved = 0;
+        now[ch] = o;
+        if (record) {
+            const int s = *counter;
+            if (s < max_samples) ring[(int64_t)ch * max_samples + s] = o;
+        }
+    }
+}
+
+__global__ void k_bump(int32_t* counter) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *counter = *counter + 1;
+}
+
+template <int BX>
+hipError_t launch_fused_bx(const Chan* chans, const TileDesc* tiles, int ntiles, int grid,
+                           float* ws, int src, hipStream_t s) {
+    const int vtotal = 8 * ((ntiles + 7) / 8);
+    const int g = grid > 0 ? min(grid, vtotal) : vtotal;
+    hipLaunchKernelGGL(k_step_fused<BX>, dim3(g), dim3(BX), 0, s, chans, tiles, ntiles, vtotal, ws,
+                       src);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_init(const Chan* chans, const RowRef* rows, int nrows, float* ws, hipStream_t s) {
+    hipLaunchKernelGGL(k_init, dim3(nrows), dim3(kRowThreads), 0, s, chans, rows, ws);
+    return hipGetLastError();
+}
+
+hipError_t launch_step_fused(int bx, const Chan* chans, const TileDesc* tiles, int ntiles, int grid,
+                             float* ws, int src, hipStream_t s) {
+    switch (bx) {
+        case 64: return launch_fused_bx<64>(chans, tiles, ntiles, grid, ws, src, s);
+        case 128: return launch_fused_bx<128>(chans, tiles, ntiles, grid, ws, src, s);
+        case 256: return launch_fused_bx<256>(chans, tiles, ntiles, grid, ws, src, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_step_two_kernel(const Chan* chans, const RowRef* rows, int nrows, float* ws,
+                                  int src, hipStream_t s) {
+    hipLaunchKernelGGL(k_density, dim3(nrows), dim3(kRowThreads), 0, s, chans, rows, ws, src);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_collide, dim3(nrows), dim3(kRowThreads), 0, s, chans, rows, ws, src);
+    return hipGetLastError();
+}
+
+hipError_t launch_observe(const Chan* chans, const RowRef* rows, int nrows, int nchan, float* ws,
+                          int src, RowPartial* partials, ObsRec* now, ObsRec* ring,
+                          int32_t* counter, int max_samples, int record, hipStream_t s) {
+    hipLaunchKernelGGL(k_obs_rows, dim3(nrows), dim3(kRowThreads), 0, s, chans, rows, ws, src,
+                       partials);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_obs_final, dim3(nchan), dim3(kRowThreads), 0, s, chans, ws, partials, now,
+                       ring, counter, max_samples, record);
+    e = hipGetLastError();
+    if (e != hipSuccess || !record) return e;
+    hipLaunchKernelGGL(k_bump, dim3(1), dim3(64), 0, s, counter);
+    return hipGetLastError();
+}
+
+hipError_t launch_pull_out(const Chan* chans, const RowRef* rows, int nrows, float* ws, int src,
+                           hipStream_t s) {
+    hipLaunchKernelGGL(k_pull_out, dim3(nrows), dim3(kRowThreads), 0, s, chans, rows, ws, src);
+    return hipGetLastError();
+}
+
+}  // namespace scf

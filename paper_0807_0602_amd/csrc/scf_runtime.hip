@@ -1,0 +1,646 @@
+// Host runtime of libscf: the C ABI of include/scf.h.
+//
+// One Engine serves both the single-channel context and the batch: a set of channels packed
+// into the caller's device workspace, a tile list for the fused step, a row list for the
+// per-row kernels, HIP graphs of captured step loops and the observation ring.  The library
+// never allocates device memory; it only carves the caller's workspace.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <limits>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "scf.h"
+#include "scf_internal.h"
+
+namespace {
+
+thread_local std::string g_err = "";
+
+int fail(int code, const std::string& msg) {
+    g_err = msg;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                  \
+    do {                                                                               \
+        hipError_t e_ = (expr);                                                        \
+        if (e_ != hipSuccess)                                                          \
+            return fail(SCF_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+int pitch_of(int nx) { return (nx + 63) / 64 * 64; }
+
+constexpr int kMaxRowsPerGeom = 1 << 20;
+constexpr int kPlanesPerChannel = 38;   // 2 x 18 population planes + 2 density planes
+
+bool geom_ok(const scf_geometry* g, std::string* why) {
+    if (!g) { *why = "geometry is NULL"; return false; }
+    if (g->nx < 3 || g->ny < 3 || g->nx >= kMaxRowsPerGeom || g->ny >= kMaxRowsPerGeom) {
+        *why = "nx and ny must be in [3, 2^20)";
+        return false;
+    }
+    if (g->x0 < 0 || g->x1 < g->x0 || g->x1 > g->nx) {
+        *why = "need 0 <= x0 <= x1 <= nx";
+        return false;
+    }
+    if ((int64_t)g->ny * pitch_of(g->nx) > (int64_t)std::numeric_limits<int32_t>::max()) {
+        *why = "ny * nx too large for one channel";
+        return false;
+    }
+    return true;
+}
+
+bool params_ok(const scf_params* p, std::string* why) {
+    if (!p) { *why = "params is NULL"; return false; }
+    for (int k = 0; k < 2; ++k) {
+        if (!(p->tau[k] > 0.5) || !std::isfinite(p->tau[k])) { *why = "tau must be > 1/2"; return false; }
+        if (!(p->alpha[k] >= 0.0 && p->alpha[k] < 1.0)) { *why = "alpha must be in [0, 1)"; return false; }
+        if (!(p->mass[k] > 0.0) || !std::isfinite(p->mass[k])) { *why = "mass must be > 0"; return false; }
+        if (!std::isfinite(p->gw[k])) { *why = "gw must be finite"; return false; }
+    }
+    if (!std::isfinite(p->G)) { *why = "G must be finite"; return false; }
+    return true;
+}
+
+struct Layout {
+    size_t chans = 0, rows = 0, tiles = 0, parts = 0, now = 0, ring = 0, counter = 0;
+    std::vector<size_t> chan_off;   // byte offset of each channel's region
+    size_t total = 0;
+    int nrows = 0, max_tiles = 0;
+};
+
+int max_tiles_of(const scf_geometry& g) { return ((g.nx + 63) / 64) * g.ny; }
+
+Layout plan(int nchan, const scf_geometry* g, int max_samples) {
+    Layout L;
+    size_t off = 0;
+    L.chans = off; off = align_up(off + sizeof(scf::Chan) * nchan, 256);
+    for (int c = 0; c < nchan; ++c) { L.nrows += g[c].ny; L.max_tiles += max_tiles_of(g[c]); }
+    L.rows = off; off = align_up(off + sizeof(scf::RowRef) * L.nrows, 256);
+    L.tiles = off; off = align_up(off + sizeof(scf::TileDesc) * L.max_tiles, 256);
+    L.parts = off; off = align_up(off + sizeof(scf::RowPartial) * L.nrows, 256);
+    L.now = off; off = align_up(off + sizeof(scf::ObsRec) * nchan, 256);
+    L.ring = off; off = align_up(off + sizeof(scf::ObsRec) * (size_t)nchan * max_samples, 256);
+    L.counter = off; off = align_up(off + 256, 256);
+    for (int c = 0; c < nchan; ++c) {
+        L.chan_off.push_back(off);
+        off = align_up(off + sizeof(float) * kPlanesPerChannel * (size_t)g[c].ny * pitch_of(g[c].nx), 256);
+    }
+    L.total = off;
+    return L;
+}
+
+scf::Chan make_chan(const scf_geometry& g, const scf_params& p, size_t byte_off, int row_base) {
+    scf::Chan c;
+    std::memset(&c, 0, sizeof c);
+    c.nx = g.nx; c.ny = g.ny; c.pitch = pitch_of(g.nx); c.x0 = g.x0; c.x1 = g.x1; c.xs = g.x0 / 2;
+    c.row_base = row_base;
+    c.off = (int64_t)(byte_off / sizeof(float));
+    c.plane = (int64_t)g.ny * c.pitch;
+    c.G = (float)p.G;
+    for (int k = 0; k < 2; ++k) {
+        c.gw[k] = (float)p.gw[k];
+        c.omega[k] = (float)(1.0 / p.tau[k]);
+        c.tm[k] = (float)(p.tau[k] / p.mass[k]);
+        c.wm[k] = (float)(p.mass[k] / p.tau[k]);
+        c.c1[k] = (float)((1.0 - p.alpha[k]) / 5.0);
+        c.c0[k] = (float)p.alpha[k];
+        c.inv_m[k] = (float)(1.0 / p.mass[k]);
+    }
+    return c;
+}
+
+}  // namespace
+
+struct Engine {
+    int nchan = 0;
+    std::vector<scf_geometry> geom;
+    std::vector<scf_params> prm;
+    std::vector<scf::Chan> chans;
+    Layout lay;
+    char* ws = nullptr;
+    size_t ws_bytes = 0;
+    hipStream_t stream = nullptr;
+    hipStream_t cap = nullptr;   // capture-only stream (nothing executes on it)
+    int cur = 0;
+    int64_t t = 0;
+    int variant = SCF_VARIANT_FUSED;
+    int bx = 256, cy = 64, graph_steps = 64, grid = 0;
+    int ntiles = 0;
+    hipGraphExec_t g_steps[2] = {nullptr, nullptr};
+    hipGraphExec_t g_sample[2] = {nullptr, nullptr};
+    int sample_every = 0, max_samples = 1;
+    int64_t recorded = 0;
+    bool batch = false;
+
+    scf::Chan* d_chans() const { return reinterpret_cast<scf::Chan*>(ws + lay.chans); }
+    scf::RowRef* d_rows() const { return reinterpret_cast<scf::RowRef*>(ws + lay.rows); }
+    scf::TileDesc* d_tiles() const { return reinterpret_cast<scf::TileDesc*>(ws + lay.tiles); }
+    scf::RowPartial* d_parts() const { return reinterpret_cast<scf::RowPartial*>(ws + lay.parts); }
+    scf::ObsRec* d_now() const { return reinterpret_cast<scf::ObsRec*>(ws + lay.now); }
+    scf::ObsRec* d_ring() const { return reinterpret_cast<scf::ObsRec*>(ws + lay.ring); }
+    int32_t* d_counter() const { return reinterpret_cast<int32_t*>(ws + lay.counter); }
+    float* base() const { return reinterpret_cast<float*>(ws); }
+
+    ~Engine() {
+        drop_graphs();
+        if (cap) (void)hipStreamDestroy(cap);
+    }
+
+    void drop_graphs() {
+        for (int p = 0; p < 2; ++p) {
+            if (g_steps[p]) (void)hipGraphExecDestroy(g_steps[p]);
+            if (g_sample[p]) (void)hipGraphExecDestroy(g_sample[p]);
+            g_steps[p] = g_sample[p] = nullptr;
+        }
+    }
+
+    std::vector<scf::TileDesc> make_tiles(int bxv, int cyv) const {
+        std::vector<scf::TileDesc> tl;
+        for (int c = 0; c < nchan; ++c) {
+            const scf_geometry& g = geom[c];
+            const int chunk = std::min(cyv, g.ny);
+            for (int xb = 0; xb < g.nx; xb += bxv)
+                for (int yb = 0; yb < g.ny; yb += chunk)
+                    tl.push_back({c, xb, yb, std::min(yb + chunk, g.ny)});
+        }
+        return tl;
+    }
+
+    int upload_tiles(int bxv, int cyv) {
+        std::vector<scf::TileDesc> tl = make_tiles(bxv, cyv);
+        if ((int)tl.size() > lay.max_tiles) return fail(SCF_EINVAL, "tile list exceeds its reserved space");
+        HIP_TRY(hipMemcpyAsync(d_tiles(), tl.data(), sizeof(scf::TileDesc) * tl.size(),
+                               hipMemcpyHostToDevice, stream));
+        HIP_TRY(hipStreamSynchronize(stream));
+        ntiles = (int)tl.size();
+        bx = bxv;
+        cy = cyv;
+        return SCF_OK;
+    }
+
+    hipError_t launch_step(hipStream_t s, int src) const {
+        if (variant == SCF_VARIANT_TWO_KERNEL)
+            return scf::launch_step_two_kernel(d_chans(), d_rows(), lay.nrows, base(), src, s);
+        return scf::launch_step_fused(bx, d_chans(), d_tiles(), ntiles, grid, base(), src, s);
+    }
+
+    hipError_t launch_obs(hipStream_t s, int record) const {
+        return scf::launch_observe(d_chans(), d_rows(), lay.nrows, nchan, base(), cur,
+                                   d_parts(), d_now(), d_ring(), d_counter(), max_samples, record, s);
+    }
+
+    // Capture `n` steps starting from parity p, optionally followed by a recorded observation.
+    int capture(int p, int n, bool observe, hipGraphExec_t* out) {
+        if (!cap) HIP_TRY(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+        hipGraph_t graph = nullptr;
+        HIP_TRY(hipStreamBeginCapture(cap, hipStreamCaptureModeRelaxed));
+        hipError_t err = hipSuccess;
+        int src = p;
+        for (int i = 0; i < n && err == hipSuccess; ++i) {
+            err = launch_step(cap, src);
+            src ^= 1;
+        }
+        if (err == hipSuccess && observe)
+            err = scf::launch_observe(d_chans(), d_rows(), lay.nrows, nchan, base(), src, d_parts(),
+                                      d_now(), d_ring(), d_counter(), max_samples, 1, cap);
+        hipError_t end = hipStreamEndCapture(cap, &graph);
+        if (err != hipSuccess) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return fail(SCF_EDEVICE, std::string("launch during capture: ") + hipGetErrorString(err));
+        }
+        if (end != hipSuccess) return fail(SCF_EDEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(end));
+        hipError_t inst = hipGraphInstantiate(out, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (inst != hipSuccess) return fail(SCF_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(inst));
+        return SCF_OK;
+    }
+
+    // Advance n steps with no observation.
+    int advance(int64_t n) {
+        while (n > 0) {
+            if (graph_steps > 0 && n >= graph_steps) {
+                if (!g_steps[cur]) {
+                    int rc = capture(cur, graph_steps, false, &g_steps[cur]);
+                    if (rc) return rc;
+                }
+                HIP_TRY(hipGraphLaunch(g_steps[cur], stream));
+                cur ^= (graph_steps & 1);
+                t += graph_steps;
+                n -= graph_steps;
+            } else {
+                HIP_TRY(launch_step(stream, cur));
+                cur ^= 1;
+                t += 1;
+                n -= 1;
+            }
+        }
+        return SCF_OK;
+    }
+
+    int observe_record() {
+        HIP_TRY(scf::launch_observe(d_chans(), d_rows(), lay.nrows, nchan, base(), cur, d_parts(),
+                                    d_now(), d_ring(), d_counter(), max_samples, 1, stream));
+        recorded += 1;
+        return SCF_OK;
+    }
+
+    // Advance n steps, recording every sample_every steps (batch mode).
+    int advance_sampled(int64_t n) {
+        const int S = sample_every;
+        while (n > 0) {
+            const int64_t phase = t % S;
+            if (phase == 0 && n >= S && graph_steps > 0 && S <= 4096) {
+                if (!g_sample[cur]) {
+                    int rc = capture(cur, S, true, &g_sample[cur]);
+                    if (rc) return rc;
+                }
+                HIP_TRY(hipGraphLaunch(g_sample[cur], stream));
+                cur ^= (S & 1);
+                t += S;
+                n -= S;
+                recorded += 1;
+                continue;
+            }
+            const int64_t m = std::min<int64_t>(n, S - phase);
+            int rc = advance(m);
+            if (rc) return rc;
+            n -= m;
+            if (t % S == 0) {
+                rc = observe_record();
+                if (rc) return rc;
+            }
+        }
+        return SCF_OK;
+    }
+
+    int setup(int nch, const scf_geometry* g, const scf_params* p, const double* const* rhoA,
+              const double* const* rhoB, int samp_every, int max_samp, void* dev_ws, size_t bytes,
+              void* s) {
+        std::string why;
+        if (nch < 1) return fail(SCF_EINVAL, "nchan must be >= 1");
+        if (!dev_ws) return fail(SCF_EINVAL, "device workspace is NULL");
+        if (reinterpret_cast<uintptr_t>(dev_ws) % 256) return fail(SCF_EINVAL, "workspace must be 256-byte aligned");
+        for (int c = 0; c < nch; ++c) {
+            if (!geom_ok(&g[c], &why)) return fail(SCF_EINVAL, "channel " + std::to_string(c) + ": " + why);
+            if (!params_ok(&p[c], &why)) return fail(SCF_EINVAL, "channel " + std::to_string(c) + ": " + why);
+            if (!rhoA || !rhoB || !rhoA[c] || !rhoB[c]) return fail(SCF_EINVAL, "density field is NULL");
+        }
+        if (max_samp < 1) return fail(SCF_EINVAL, "max_samples must be >= 1");
+        nchan = nch;
+        geom.assign(g, g + nch);
+        prm.assign(p, p + nch);
+        lay = plan(nch, g, max_samp);
+        if (bytes < lay.total)
+            return fail(SCF_EINVAL, "workspace too small: need " + std::to_string(lay.total) + " bytes");
+        ws = static_cast<char*>(dev_ws);
+        ws_bytes = bytes;
+        stream = static_cast<hipStream_t>(s);
+        sample_every = samp_every;
+        max_samples = max_samp;
+        std::vector<scf::RowRef> rows;
+        int row_base = 0;
+        for (int c = 0; c < nch; ++c) {
+            chans.push_back(make_chan(g[c], p[c], lay.chan_off[c], row_base));
+            for (int y = 0; y < g[c].ny; ++y) rows.push_back({c, y});
+            row_base += g[c].ny;
+        }
+        HIP_TRY(hipMemcpyAsync(d_chans(), chans.data(), sizeof(scf::Chan) * nch, hipMemcpyHostToDevice, stream));
+        HIP_TRY(hipMemcpyAsync(d_rows(), rows.data(), sizeof(scf::RowRef) * rows.size(), hipMemcpyHostToDevice, stream));
+        HIP_TRY(hipMemsetAsync(d_counter(), 0, 256, stream));
+        // stage FP64 fields in population buffer 1 of each channel, then build buffer 0
+        for (int c = 0; c < nch; ++c) {
+            const size_t cells = (size_t)g[c].nx * g[c].ny;
+            char* stage = ws + lay.chan_off[c] + sizeof(float) * 18 * chans[c].plane;
+            HIP_TRY(hipMemcpyAsync(stage, rhoA[c], sizeof(double) * cells, hipMemcpyHostToDevice, stream));
+            HIP_TRY(hipMemcpyAsync(stage + sizeof(double) * cells, rhoB[c], sizeof(double) * cells,
+                                   hipMemcpyHostToDevice, stream));
+        }
+        HIP_TRY(scf::launch_init(d_chans(), d_rows(), lay.nrows, base(), stream));
+        cur = 0;
+        t = 0;
+        int rc = upload_tiles(bx, cy);
+        if (rc) return rc;
+        if (sample_every > 0) {
+            rc = observe_record();   // the t = 0 record
+            if (rc) return rc;
+        }
+        HIP_TRY(hipStreamSynchronize(stream));
+        return SCF_OK;
+    }
+
+    int set_tile(int bxv, int cyv, int gsteps) {
+        if (bxv != 64 && bxv != 128 && bxv != 256) return fail(SCF_EINVAL, "bx must be 64, 128 or 256");
+        if (cyv < 1) return fail(SCF_EINVAL, "cy must be >= 1");
+        if (gsteps < 0) return fail(SCF_EINVAL, "graph_steps must be >= 0");
+        HIP_TRY(hipStreamSynchronize(stream));
+        drop_graphs();
+        graph_steps = gsteps;
+        return upload_tiles(bxv, cyv);
+    }
+
+    // Time each candidate by repeated steps that all read the resident buffer and write the
+    // idle one, so the state is never modified.
+    int autotune(int trial, int32_t* obx, int32_t* ocy) {
+        if (trial < 1) return fail(SCF_EINVAL, "trial_steps must be >= 1");
+        HIP_TRY(hipStreamSynchronize(stream));
+        int maxny = 0;
+        for (auto& g : geom) maxny = std::max(maxny, g.ny);
+        const int bxs[3] = {64, 128, 256};
+        const int cys[6] = {8, 16, 32, 64, 128, 1 << 30};
+        hipEvent_t e0, e1;
+        HIP_TRY(hipEventCreate(&e0));
+        HIP_TRY(hipEventCreate(&e1));
+        float best = std::numeric_limits<float>::max();
+        int bbx = bx, bcy = cy;
+        const int saved_variant = variant;
+        variant = SCF_VARIANT_FUSED;
+        int rc = SCF_OK;
+        for (int bxv : bxs) {
+            for (int cyv : cys) {
+                if (cyv != (1 << 30) && cyv >= maxny) continue;
+                rc = upload_tiles(bxv, cyv);
+                if (rc) break;
+                for (int i = 0; i < 2; ++i) (void)launch_step(stream, cur);
+                (void)hipEventRecord(e0, stream);
+                for (int i = 0; i < trial; ++i) (void)launch_step(stream, cur);
+                (void)hipEventRecord(e1, stream);
+                if (hipEventSynchronize(e1) != hipSuccess) { rc = fail(SCF_EDEVICE, "autotune timing failed"); break; }
+                float ms = 0.0f;
+                (void)hipEventElapsedTime(&ms, e0, e1);
+                if (ms < best) { best = ms; bbx = bxv; bcy = cyv; }
+            }
+            if (rc) break;
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        variant = saved_variant;
+        if (rc) return rc;
+        drop_graphs();
+        rc = upload_tiles(bbx, bcy);
+        if (rc) return rc;
+        if (obx) *obx = bbx;
+        if (ocy) *ocy = bcy;
+        return SCF_OK;
+    }
+
+    int get_density(int c, double* nA, double* nB) {
+        if (c < 0 || c >= nchan || !nA || !nB) return fail(SCF_EINVAL, "bad channel or NULL output");
+        HIP_TRY(launch_obs(stream, 0));
+        const scf_geometry& g = geom[c];
+        const int pitch = chans[c].pitch;
+        std::vector<float> h((size_t)2 * g.ny * pitch);
+        HIP_TRY(hipMemcpyAsync(h.data(), ws + lay.chan_off[c] + sizeof(float) * 36 * chans[c].plane,
+                               sizeof(float) * h.size(), hipMemcpyDeviceToHost, stream));
+        HIP_TRY(hipStreamSynchronize(stream));
+        for (int y = 0; y < g.ny; ++y)
+            for (int x = 0; x < g.nx; ++x) {
+                nA[(size_t)y * g.nx + x] = h[(size_t)y * pitch + x];
+                nB[(size_t)y * g.nx + x] = h[(size_t)(g.ny + y) * pitch + x];
+            }
+        return SCF_OK;
+    }
+};
+
+struct scf_ctx { Engine e; };
+struct scf_batch { Engine e; };
+
+extern "C" {
+
+const char* scf_last_error(void) { return g_err.c_str(); }
+
+size_t scf_workspace_bytes(const scf_geometry* geom) {
+    std::string why;
+    if (!geom_ok(geom, &why)) return 0;
+    return plan(1, geom, 1).total;
+}
+
+int scf_init(scf_ctx** out, const scf_geometry* geom, const scf_params* params, const double* rhoA,
+             const double* rhoB, void* dev_ws, size_t ws_bytes, void* hip_stream) {
+    if (!out) return fail(SCF_EINVAL, "out is NULL");
+    *out = nullptr;
+    scf_ctx* c = new (std::nothrow) scf_ctx();
+    if (!c) return fail(SCF_ENOMEM, "out of host memory");
+    const double* a[1] = {rhoA};
+    const double* b[1] = {rhoB};
+    int rc = c->e.setup(1, geom, params, a, b, 0, 1, dev_ws, ws_bytes, hip_stream);
+    if (rc) { delete c; return rc; }
+    *out = c;
+    return SCF_OK;
+}
+
+int scf_step(scf_ctx* ctx, int64_t nsteps) {
+    if (!ctx || nsteps < 0) return fail(SCF_EINVAL, "bad context or negative step count");
+    return ctx->e.advance(nsteps);
+}
+
+int scf_observe(scf_ctx* ctx, scf_obs* out) {
+    if (!ctx || !out) return fail(SCF_EINVAL, "NULL argument");
+    Engine& e = ctx->e;
+    HIP_TRY(e.launch_obs(e.stream, 0));
+    scf::ObsRec r;
+    HIP_TRY(hipMemcpyAsync(&r, e.d_now(), sizeof r, hipMemcpyDeviceToHost, e.stream));
+    HIP_TRY(hipStreamSynchronize(e.stream));
+    static_assert(sizeof(scf::ObsRec) == sizeof(scf_obs), "record layout");
+    std::memcpy(out, &r, sizeof r);
+    out->t = e.t;
+    if (out->flags & 2) return fail(SCF_EUNSTABLE, "non-finite or negative density in the state");
+    return SCF_OK;
+}
+
+int scf_get_density(scf_ctx* ctx, double* nA, double* nB) {
+    if (!ctx) return fail(SCF_EINVAL, "NULL context");
+    return ctx->e.get_density(0, nA, nB);
+}
+
+int scf_get_populations(scf_ctx* ctx, double* f) {
+    if (!ctx || !f) return fail(SCF_EINVAL, "NULL argument");
+    Engine& e = ctx->e;
+    HIP_TRY(scf::launch_pull_out(e.d_chans(), e.d_rows(), e.lay.nrows, e.base(), e.cur, e.stream));
+    const scf_geometry& g = e.geom[0];
+    const int pitch = e.chans[0].pitch;
+    const int64_t P = e.chans[0].plane;
+    std::vector<float> h((size_t)18 * P);
+    HIP_TRY(hipMemcpyAsync(h.data(), e.ws + e.lay.chan_off[0] + sizeof(float) * (size_t)(e.cur ^ 1) * 18 * P,
+                           sizeof(float) * h.size(), hipMemcpyDeviceToHost, e.stream));
+    HIP_TRY(hipStreamSynchronize(e.stream));
+    for (int q = 0; q < 18; ++q)
+        for (int y = 0; y < g.ny; ++y)
+            for (int x = 0; x < g.nx; ++x)
+                f[((size_t)q * g.ny + y) * g.nx + x] = h[(size_t)q * P + (size_t)y * pitch + x];
+    return SCF_OK;
+}
+
+int scf_set_variant(scf_ctx* ctx, int32_t variant) {
+    if (!ctx) return fail(SCF_EINVAL, "NULL context");
+    if (variant != SCF_VARIANT_FUSED && variant != SCF_VARIANT_TWO_KERNEL)
+        return fail(SCF_EINVAL, "unknown variant");
+    HIP_TRY(hipStreamSynchronize(ctx->e.stream));
+    ctx->e.drop_graphs();
+    ctx->e.variant = variant;
+    return SCF_OK;
+}
+
+int scf_set_tile(scf_ctx* ctx, int32_t bx, int32_t cy, int32_t graph_steps) {
+    if (!ctx) return fail(SCF_EINVAL, "NULL context");
+    return ctx->e.set_tile(bx, cy, graph_steps);
+}
+
+int scf_autotune(scf_ctx* ctx, int32_t trial_steps, int32_t* bx, int32_t* cy) {
+    if (!ctx) return fail(SCF_EINVAL, "NULL context");
+    return ctx->e.autotune(trial_steps, bx, cy);
+}
+
+int64_t scf_time(const scf_ctx* ctx) { return ctx ? ctx->e.t : -1; }
+
+namespace {
+struct CkptHeader {
+    char magic[8];
+    int32_t version, nchan;
+    scf_geometry geom;
+    scf_params params;
+    int64_t t;
+    int64_t floats;
+};
+}  // namespace
+
+int scf_save(scf_ctx* ctx, const char* path) {
+    if (!ctx || !path) return fail(SCF_EINVAL, "NULL argument");
+    Engine& e = ctx->e;
+    CkptHeader h;
+    std::memset(&h, 0, sizeof h);
+    std::memcpy(h.magic, "SCFCKPT1", 8);
+    h.version = 1;
+    h.nchan = 1;
+    h.geom = e.geom[0];
+    h.params = e.prm[0];
+    h.t = e.t;
+    h.floats = 18 * e.chans[0].plane;
+    std::vector<float> buf((size_t)h.floats);
+    HIP_TRY(hipMemcpyAsync(buf.data(), e.ws + e.lay.chan_off[0] + sizeof(float) * (size_t)e.cur * 18 * e.chans[0].plane,
+                           sizeof(float) * buf.size(), hipMemcpyDeviceToHost, e.stream));
+    HIP_TRY(hipStreamSynchronize(e.stream));
+    FILE* f = std::fopen(path, "wb");
+    if (!f) return fail(SCF_EINVAL, std::string("cannot open ") + path);
+    bool ok = std::fwrite(&h, sizeof h, 1, f) == 1 &&
+              std::fwrite(buf.data(), sizeof(float), buf.size(), f) == buf.size();
+    ok = (std::fclose(f) == 0) && ok;
+    return ok ? SCF_OK : fail(SCF_ESTATE, std::string("write failed: ") + path);
+}
+
+int scf_load(scf_ctx* ctx, const char* path) {
+    if (!ctx || !path) return fail(SCF_EINVAL, "NULL argument");
+    Engine& e = ctx->e;
+    FILE* f = std::fopen(path, "rb");
+    if (!f) return fail(SCF_EINVAL, std::string("cannot open ") + path);
+    CkptHeader h;
+    bool ok = std::fread(&h, sizeof h, 1, f) == 1 && std::memcmp(h.magic, "SCFCKPT1", 8) == 0 &&
+              h.version == 1 && h.nchan == 1 && std::memcmp(&h.geom, &e.geom[0], sizeof h.geom) == 0 &&
+              std::memcmp(&h.params, &e.prm[0], sizeof h.params) == 0 &&
+              h.floats == 18 * e.chans[0].plane;
+    std::vector<float> buf;
+    if (ok) {
+        buf.resize((size_t)h.floats);
+        ok = std::fread(buf.data(), sizeof(float), buf.size(), f) == buf.size();
+    }
+    std::fclose(f);
+    if (!ok) return fail(SCF_ESTATE, std::string("checkpoint does not match this context: ") + path);
+    HIP_TRY(hipStreamSynchronize(e.stream));
+    HIP_TRY(hipMemcpyAsync(e.ws + e.lay.chan_off[0] + sizeof(float) * (size_t)e.cur * 18 * e.chans[0].plane,
+                           buf.data(), sizeof(float) * buf.size(), hipMemcpyHostToDevice, e.stream));
+    HIP_TRY(hipStreamSynchronize(e.stream));
+    e.t = h.t;
+    return SCF_OK;
+}
+
+void scf_destroy(scf_ctx* ctx) {
+    if (!ctx) return;
+    (void)hipStreamSynchronize(ctx->e.stream);
+    delete ctx;
+}
+
+size_t scf_batch_workspace_bytes(int32_t nchan, const scf_geometry* geoms, int32_t max_samples) {
+    if (nchan < 1 || !geoms || max_samples < 1) return 0;
+    std::string why;
+    for (int c = 0; c < nchan; ++c)
+        if (!geom_ok(&geoms[c], &why)) return 0;
+    return plan(nchan, geoms, max_samples).total;
+}
+
+int scf_batch_init(scf_batch** out, int32_t nchan, const scf_geometry* geoms, const scf_params* params,
+                   const double* const* rhoA, const double* const* rhoB, int32_t sample_every,
+                   int32_t max_samples, void* dev_ws, size_t ws_bytes, void* hip_stream) {
+    if (!out) return fail(SCF_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (sample_every < 1) return fail(SCF_EINVAL, "sample_every must be >= 1");
+    if (!geoms || !params) return fail(SCF_EINVAL, "NULL geometry or params");
+    scf_batch* b = new (std::nothrow) scf_batch();
+    if (!b) return fail(SCF_ENOMEM, "out of host memory");
+    b->e.batch = true;
+    int rc = b->e.setup(nchan, geoms, params, rhoA, rhoB, sample_every, max_samples, dev_ws, ws_bytes,
+                        hip_stream);
+    if (rc) { delete b; return rc; }
+    *out = b;
+    return SCF_OK;
+}
+
+int scf_batch_step(scf_batch* b, int64_t nsteps) {
+    if (!b || nsteps < 0) return fail(SCF_EINVAL, "bad batch or negative step count");
+    return b->e.advance_sampled(nsteps);
+}
+
+int scf_batch_observe(scf_batch* b, scf_obs* out, int64_t* nsamples) {
+    if (!b || !out || !nsamples) return fail(SCF_EINVAL, "NULL argument");
+    Engine& e = b->e;
+    const size_t n = (size_t)e.nchan * e.max_samples;
+    std::vector<scf::ObsRec> h(n);
+    HIP_TRY(hipMemcpyAsync(h.data(), e.d_ring(), sizeof(scf::ObsRec) * n, hipMemcpyDeviceToHost, e.stream));
+    HIP_TRY(hipStreamSynchronize(e.stream));
+    const int64_t have = std::min<int64_t>(e.recorded, e.max_samples);
+    bool unstable = false;
+    for (int c = 0; c < e.nchan; ++c)
+        for (int64_t s = 0; s < e.max_samples; ++s) {
+            scf_obs& o = out[(size_t)c * e.max_samples + s];
+            std::memcpy(&o, &h[(size_t)c * e.max_samples + s], sizeof o);
+            if (s < have) {
+                o.t = s * (int64_t)e.sample_every;
+                if (o.flags & 2) unstable = true;
+            } else {
+                std::memset(&o, 0, sizeof o);
+                o.t = -1;
+            }
+        }
+    *nsamples = have;
+    if (unstable) return fail(SCF_EUNSTABLE, "a recorded sample holds a non-finite or negative density");
+    return SCF_OK;
+}
+
+int scf_batch_get_density(scf_batch* b, int32_t c, double* nA, double* nB) {
+    if (!b) return fail(SCF_EINVAL, "NULL batch");
+    return b->e.get_density(c, nA, nB);
+}
+
+int scf_batch_set_tile(scf_batch* b, int32_t bx, int32_t cy, int32_t graph_steps) {
+    if (!b) return fail(SCF_EINVAL, "NULL batch");
+    return b->e.set_tile(bx, cy, graph_steps);
+}
+
+int scf_batch_autotune(scf_batch* b, int32_t trial_steps, int32_t* bx, int32_t* cy) {
+    if (!b) return fail(SCF_EINVAL, "NULL batch");
+    return b->e.autotune(trial_steps, bx, cy);
+}
+
+void scf_batch_destroy(scf_batch* b) {
+    if (!b) return;
+    (void)hipStreamSynchronize(b->e.stream);
+    delete b;
+}
+
+}  // extern "C"

@@ -1,0 +1,61 @@
+"""The C ABI library loads and exports every function include/scf.h declares (no GPU calls)."""
+import os
+import re
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    text = open(os.path.join(ROOT, "include", "scf.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(scf_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_calls():
+    names = _declared()
+    for n in ("scf_init", "scf_step", "scf_observe", "scf_batch_init", "scf_batch_step",
+              "scf_batch_observe", "scf_last_error", "scf_save", "scf_load"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    import ctypes
+    from paper_0807_0602_amd import _lib
+    lib = ctypes.CDLL(_lib.LIB_PATH)
+    missing = [n for n in _declared() if not hasattr(lib, n)]
+    assert not missing, missing
+    assert set(_declared()) == set(_lib.EXPORTED)
+
+
+def test_workspace_sizes_and_validation():
+    import ctypes as C
+    from paper_0807_0602_amd import _lib as L
+    g = L.scf_geometry(200, 24, 50, 150)
+    n = L.scf_workspace_bytes(C.byref(g))
+    pitch = 256
+    assert n >= 38 * 24 * pitch * 4
+    assert L.scf_workspace_bytes(C.byref(L.scf_geometry(2, 24, 0, 0))) == 0      # nx too small
+    assert L.scf_workspace_bytes(C.byref(L.scf_geometry(200, 24, 150, 50))) == 0  # x1 < x0
+    gs = (L.scf_geometry * 2)(L.scf_geometry(200, 24, 50, 150), L.scf_geometry(96, 22, 24, 72))
+    assert L.scf_batch_workspace_bytes(2, gs, 10) > n
+
+
+def test_init_rejects_bad_arguments_without_touching_the_device():
+    import ctypes as C
+    import numpy as np
+    from paper_0807_0602_amd import _lib as L
+    g = L.scf_geometry(200, 24, 50, 150)
+    p = L.scf_params()
+    p.G = 0.9
+    for k in range(2):
+        p.tau[k] = 1.0; p.alpha[k] = 4 / 9; p.mass[k] = 1.0
+    a = np.zeros((24, 200))
+    h = C.c_void_p()
+    dp = lambda x: x.ctypes.data_as(C.POINTER(C.c_double))
+    # NULL workspace
+    assert L.scf_init(C.byref(h), C.byref(g), C.byref(p), dp(a), dp(a), None, 0, None) == L.SCF_EINVAL
+    # tau <= 1/2 is rejected before any device work
+    p.tau[1] = 0.5
+    assert L.scf_init(C.byref(h), C.byref(g), C.byref(p), dp(a), dp(a), C.c_void_p(256), 1 << 30,
+                      None) == L.SCF_EINVAL
+    assert b"tau" in L.scf_last_error()

@@ -1,0 +1,332 @@
+"""GPU parity: the FP32 HIP path against the FP64 CPU oracle on the same seeded inputs.
+
+Bar (FP32 state vs FP64 oracle): max |n_k^GPU - n_k^oracle| <= 1e-5 after 1000 steps of the
+200 x 24 capillary, |z^GPU - z^oracle| <= 0.5 lattice units through 2000 steps.  Variants of
+the GPU path (tile shapes, graph or eager launches, fused or two-kernel, batched or solo,
+checkpoint round trip) must agree bit for bit: they run identical per-node arithmetic.
+"""
+import math
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_0807_0602_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+RHO_TOL = 1e-5
+Z_TOL = 0.5
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def scf():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_0807_0602_amd import scf as S
+    return S
+
+
+def _oracle_run(case, steps):
+    return oracle.Oracle.from_case(case).init(*case.fields()).step(steps)
+
+
+# ------------------------------------------------------------------------------ populations
+@pytest.mark.parametrize("steps", [0, 1, 2, 7])
+def test_populations_first_steps(scf, steps):
+    case = inputs.capillary_small(seed=1)
+    _say(f"case: populations {case.name} steps={steps}")
+    ch = scf.Channel.from_case(case)
+    ch.step(steps)
+    f = ch.populations()
+    ref = _oracle_run(case, steps).populations()
+    np.testing.assert_allclose(f, ref, rtol=0, atol=2e-6)
+
+
+# ------------------------------------------------------------------------------ densities
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_density_parity_1000_steps(scf, seed):
+    case = inputs.capillary_small(seed=seed)
+    _say(f"case: density parity {case.name} seed={seed} 1000 steps")
+    ch = scf.Channel.from_case(case)
+    ch.step(1000)
+    nA, nB = ch.density()
+    rA, rB = _oracle_run(case, 1000).density()
+    err = max(np.abs(nA - rA).max(), np.abs(nB - rB).max())
+    _say(f"  max|drho| = {err:.3e}")
+    assert err <= RHO_TOL
+
+
+def test_front_and_mass_through_2000_steps(scf):
+    case = inputs.capillary_small(seed=1)
+    _say(f"case: z(t) parity {case.name} 2000 steps, every 10")
+    ch = scf.Channel.from_case(case)
+    orc = oracle.Oracle.from_case(case).init(*case.fields())
+    m0 = ch.observe()["mass"]
+    worst_z = worst_p = 0.0
+    for t in range(0, 2001, 10):
+        if t:
+            ch.step(10)
+            orc.step(10)
+        g, r = ch.observe(), orc.observe()
+        assert g["t"] == r["t"] == t
+        worst_z = max(worst_z, abs(g["z"] - r["z"]))
+        worst_p = max(worst_p, abs(g["precursor"] - r["precursor"]))
+        assert g["flags"] == r["flags"]
+        for k in range(2):
+            assert abs(g["mass"][k] - r["mass"][k]) / r["mass"][k] < 1e-5
+    _say(f"  max|dz| = {worst_z:.3e}  max|dp| = {worst_p:.3e}")
+    assert worst_z <= Z_TOL
+    assert worst_p <= Z_TOL
+    m1 = ch.observe()["mass"]
+    for k in range(2):
+        assert abs(m1[k] - m0[k]) / m0[k] < 1e-5     # FP32 drift stays small
+
+
+# ------------------------------------------------------------------------------ edge geometries
+EDGE_CASES = [
+    # (name, geometry, params, fields builder)
+    ("no_walls_periodic", inputs.Geometry(70, 9, 0, 0), inputs.Params(gw=(0.0, 0.0))),
+    ("fully_walled", inputs.Geometry(96, 13, 0, 96), inputs.Params(gw=(-0.2, 0.2))),
+    ("odd_ny_ragged_nx", inputs.Geometry(131, 17, 20, 111), inputs.Params(gw=(-0.3, 0.3), tau=(1.5, 1.0))),
+    ("tiny_box", inputs.Geometry(3, 3, 1, 2), inputs.Params(gw=(0.1, -0.1))),
+    ("wall_to_edge", inputs.Geometry(64, 10, 32, 64), inputs.Params(gw=(-0.25, 0.25), tau=(2.0, 0.8))),
+    ("general_alpha_mass", inputs.Geometry(80, 12, 20, 60),
+     inputs.Params(gw=(-0.1, 0.1), alpha=(4 / 9, 0.6), mass=(1.0, 1.5), tau=(1.2, 0.9))),
+]
+
+
+@pytest.mark.parametrize("name,geom,params", EDGE_CASES, ids=[c[0] for c in EDGE_CASES])
+def test_edge_geometries(scf, name, geom, params):
+    case = inputs.Case(geom, params, seed=5, liquid_x1=max(geom.x0, geom.nx // 3))
+    steps = 150
+    _say(f"case: edge {name} {geom} {steps} steps")
+    ch = scf.Channel.from_case(case)
+    ch.step(steps)
+    f = ch.populations()
+    ref = _oracle_run(case, steps).populations()
+    err = np.abs(f - ref).max()
+    _say(f"  max|df| = {err:.3e}")
+    assert err <= 1e-5
+
+
+# ------------------------------------------------------------------------------ bitwise variants
+def _state(ch):
+    return ch.populations()
+
+
+@pytest.mark.parametrize("bx,cy", [(64, 8), (64, 1 << 30), (128, 5), (256, 64), (256, 1), (128, 23)])
+def test_tile_shapes_bitwise(scf, bx, cy):
+    case = inputs.capillary_small(seed=2)
+    _say(f"case: tile shape bx={bx} cy={cy}")
+    a = scf.Channel.from_case(case)
+    a.step(120)
+    b = scf.Channel.from_case(case)
+    b.set_tile(bx, cy, 64)
+    b.step(120)
+    assert np.array_equal(_state(a), _state(b))
+
+
+def test_graph_vs_eager_bitwise(scf):
+    case = inputs.capillary_small(seed=3)
+    _say("case: graph vs eager")
+    a = scf.Channel.from_case(case)
+    a.set_tile(256, 64, 0)
+    a.step(257)
+    b = scf.Channel.from_case(case)
+    b.set_tile(256, 64, 32)
+    for _ in range(3):       # replay the captured graphs several times, eager tail in between
+        b.step(85)
+    b.step(2)
+    assert a.t == b.t == 257
+    assert np.array_equal(_state(a), _state(b))
+
+
+def test_two_kernel_matches_fused_bitwise(scf):
+    case = inputs.capillary_small(seed=1)
+    _say("case: two-kernel vs fused")
+    from paper_0807_0602_amd import _lib as L
+    a = scf.Channel.from_case(case)
+    a.step(300)
+    b = scf.Channel.from_case(case)
+    b.set_variant(L.SCF_VARIANT_TWO_KERNEL)
+    b.step(300)
+    assert np.array_equal(_state(a), _state(b))
+
+
+def test_checkpoint_roundtrip_bitwise(scf, tmp_path):
+    case = inputs.capillary_small(seed=1)
+    _say("case: checkpoint round trip")
+    a = scf.Channel.from_case(case)
+    a.step(400)
+    b = scf.Channel.from_case(case)
+    b.step(200)
+    p = str(tmp_path / "ck.bin")
+    b.save(p)
+    c = scf.Channel.from_case(case)
+    c.load(p)
+    assert c.t == 200
+    c.step(200)
+    assert np.array_equal(_state(a), _state(c))
+
+
+def test_checkpoint_rejects_other_geometry(scf, tmp_path):
+    from paper_0807_0602_amd import _lib as L
+    a = scf.Channel.from_case(inputs.capillary_small(seed=1))
+    p = str(tmp_path / "ck.bin")
+    a.save(p)
+    other = inputs.Case(inputs.Geometry(128, 24, 32, 96), inputs.Params(gw=(-0.2, 0.2)))
+    b = scf.Channel.from_case(other)
+    with pytest.raises(L.ScfError) as e:
+        b.load(p)
+    assert e.value.code == L.SCF_ESTATE
+
+
+# ------------------------------------------------------------------------------ errors, instability
+def test_rejects_tau_at_one_half(scf):
+    from paper_0807_0602_amd import _lib as L
+    case = inputs.with_params(inputs.capillary_small(), tau=(1.0, 0.5))
+    with pytest.raises(L.ScfError) as e:
+        scf.Channel.from_case(case)
+    assert e.value.code == L.SCF_EINVAL
+
+
+def test_instability_is_flagged(scf):
+    """tau_B = 0.55 with tau_A = 1 goes unstable on the 200 x 24 capillary: both the oracle and
+    the GPU must report it (health flag bit 1, SCF_EUNSTABLE)."""
+    from paper_0807_0602_amd import _lib as L
+    case = inputs.with_params(inputs.capillary_small(seed=1), tau=(1.0, 0.55))
+    _say("case: instability flag, tau = (1.0, 0.55)")
+    orc = oracle.Oracle.from_case(case).init(*case.fields())
+    ch = scf.Channel.from_case(case)
+    t_orc = t_gpu = None
+    for t in range(100, 3001, 100):
+        orc.step(100)
+        ch.step(100)
+        if t_orc is None and orc.observe()["flags"] & 2:
+            t_orc = t
+        if t_gpu is None:
+            o = ch.observe(allow_unstable=True)
+            if o["flags"] & 2:
+                t_gpu = t
+                with pytest.raises(L.ScfError) as e:
+                    ch.observe()
+                assert e.value.code == L.SCF_EUNSTABLE
+        if t_orc and t_gpu:
+            break
+    _say(f"  flagged at oracle t={t_orc}, gpu t={t_gpu}")
+    assert t_orc is not None and t_gpu is not None
+
+
+# ------------------------------------------------------------------------------ batched
+def test_batch_matches_solo_bitwise(scf):
+    cases = [inputs.capillary_small(seed=1),
+             inputs.sweep_channel(20, 128, -0.25, 2, seed=9, steps=300, sample_every=50),
+             inputs.Case(inputs.Geometry(131, 17, 20, 111), inputs.Params(gw=(-0.3, 0.3), tau=(2.0, 0.8)),
+                         seed=4, liquid_x1=20)]
+    _say("case: batch of 3 vs solo")
+    b = scf.Batch(cases, sample_every=50, max_samples=8)
+    b.step(300)
+    recs, ns = b.observe()
+    assert ns == 7
+    for c, case in enumerate(cases):
+        solo = scf.Channel.from_case(case)
+        for s in range(7):
+            o = solo.observe()
+            r = recs[c][s]
+            assert r["t"] == s * 50 == o["t"]
+            for key in ("z", "precursor", "precursor_lo", "precursor_hi"):
+                assert (math.isnan(r[key]) and math.isnan(o[key])) or r[key] == o[key], (c, s, key)
+            assert r["mass"] == o["mass"] and r["flags"] == o["flags"]
+            if s < 6:
+                solo.step(50)
+        da = b.density(c)
+        ds = solo.density()
+        assert np.array_equal(da[0], ds[0]) and np.array_equal(da[1], ds[1])
+
+
+def test_batch_against_oracle(scf):
+    cases = [inputs.sweep_channel(20, 128, g, r, seed=10 + i, steps=500, sample_every=100)
+             for i, (g, r) in enumerate([(-0.3, 1), (0.2, 2), (-0.1, 5), (-0.25, 10)])]
+    _say("case: batch of 4 sweep channels vs oracle, 500 steps")
+    b = scf.Batch(cases, sample_every=100, max_samples=6)
+    b.autotune(3)
+    b.step(500)
+    recs, ns = b.observe()
+    assert ns == 6
+    for c, case in enumerate(cases):
+        orc = oracle.Oracle.from_case(case).init(*case.fields())
+        for s in range(ns):
+            r, o = recs[c][s], orc.observe()
+            if not (math.isnan(r["z"]) and math.isnan(o["z"])):
+                assert abs(r["z"] - o["z"]) <= Z_TOL
+            orc.step(100)
+        nA, nB = b.density(c)
+        orc2 = oracle.Oracle.from_case(case).init(*case.fields()).step(500)
+        rA, rB = orc2.density()
+        assert max(np.abs(nA - rA).max(), np.abs(nB - rB).max()) <= RHO_TOL
+
+
+# ------------------------------------------------------------------------------ full sizes
+def _window_check(scf, case, T, centres, half):
+    """Run the full-size GPU channel T steps; for each sampled centre column, run the oracle on a
+    window of width 2*half+1 (x clamped at its edges) and compare the columns at distance > 2T
+    from the window edges, where the window's result is exact."""
+    ch = scf.Channel.from_case(case)
+    ch.step(T)
+    nA, nB = ch.density()
+    worst = 0.0
+    nx = case.geom.nx
+    for xc in centres:
+        xa = xc - half
+        w = 2 * half + 1
+        orc = oracle.Oracle.from_case(case, periodic_x=False, x_offset=xa, width=w)
+        orc.init(*case.fields(xa, xa + w)).step(T)
+        rA, rB = orc.density()
+        inner = np.arange(2 * T + 1, w - 2 * T - 1)
+        cols = (xa + inner) % nx
+        worst = max(worst, np.abs(nA[:, cols] - rA[:, inner]).max(), np.abs(nB[:, cols] - rB[:, inner]).max())
+    return worst
+
+
+def test_full_size_roofline_case_windows(scf):
+    case = inputs.capillary_roofline(seed=1)
+    T = 60
+    _say(f"case: {case.name} full size, {T} steps, oracle windows")
+    g = case.geom
+    # channel inlet, channel outlet, the x = 0 wrap, a bulk column
+    worst = _window_check(scf, case, T, [g.x0, g.x1 - 1, 0, 7000], half=2 * T + 8)
+    _say(f"  max|drho| = {worst:.3e}")
+    assert worst <= RHO_TOL
+
+
+def test_full_size_washburn_case_windows(scf):
+    case = inputs.capillary_washburn(seed=1)
+    T = 100
+    _say(f"case: {case.name} full size, {T} steps, oracle windows")
+    g = case.geom
+    worst = _window_check(scf, case, T, [g.x0, g.x1, 4095], half=2 * T + 6)
+    _say(f"  max|drho| = {worst:.3e}")
+    assert worst <= RHO_TOL
+
+
+def test_full_size_roofline_case_mass_and_observables(scf):
+    """Properties that hold at any size: mass conservation and the initial front z(0) = -1/2."""
+    case = inputs.capillary_roofline(seed=2)
+    _say(f"case: {case.name} mass over 200 steps")
+    ch = scf.Channel.from_case(case)
+    o0 = ch.observe()
+    assert abs(o0["z"] + 0.5) < 0.01
+    ch.step(200)
+    o1 = ch.observe()
+    for k in range(2):
+        assert abs(o1["mass"][k] - o0["mass"][k]) / o0["mass"][k] < 1e-5
+    assert o1["flags"] == 0
