@@ -11,7 +11,7 @@ once and written once).
 
 Prints ONE JSON line.  Options: --steps K (timed), --warmup W, --gpus N (only 1 is supported),
 --variant fused|two_kernel, --no-cpu-baseline, --calibrate-copy (runs only a plain copy kernel,
-for counter calibration under rocprofv3), --tile BX CY (skip the autotuner).
+for counter calibration under rocprofv3), --tile BX CY ORDER (skip the autotuner).
 """
 from __future__ import annotations
 
@@ -89,7 +89,7 @@ def main() -> int:
     ap.add_argument("--variant", choices=["fused", "two_kernel"], default="fused")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true")
-    ap.add_argument("--tile", type=int, nargs=2, default=None)
+    ap.add_argument("--tile", type=int, nargs=3, default=None, metavar=("BX", "CY", "ORDER"))
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU; multi-GPU runs are not part of this build "
@@ -113,10 +113,10 @@ def main() -> int:
     ch = Channel.from_case(case, stream=stream)
     variant = L.SCF_VARIANT_FUSED if args.variant == "fused" else L.SCF_VARIANT_TWO_KERNEL
     if args.tile:
-        ch.set_tile(args.tile[0], args.tile[1], 64)
-        tile = list(args.tile)
+        ch.set_tile(args.tile[0], args.tile[1], 64, args.tile[2])
     else:
-        tile = list(ch.autotune(20))
+        ch.autotune(20)
+    tile = ch.tile()
     ch.set_variant(variant)
     ch.step(args.warmup)
     torch.cuda.synchronize()
@@ -145,7 +145,7 @@ def main() -> int:
         "data": "synthetic",
         "config": {"workload": case.name, "nx": g.nx, "ny": g.ny, "channel_x": [g.x0, g.x1],
                    "G": case.params.G, "gw": list(case.params.gw), "tau": list(case.params.tau),
-                   "variant": args.variant, "tile_bx_cy": tile, "nodes": cells},
+                   "variant": args.variant, "schedule": tile, "nodes": cells},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "kernel": "k_step_fused" if args.variant == "fused" else "k_density+k_collide",

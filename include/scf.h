@@ -79,6 +79,19 @@ typedef struct {
     int32_t reserved;
 } scf_obs;
 
+/* Launch schedule of the fused step (see scf_set_tile). */
+typedef struct {
+    int32_t bx;           /* block width in nodes along x: 64, 128 or 256 */
+    int32_t cy;           /* rows per tile, >= 1 (>= ny: whole columns) */
+    int32_t order;        /* tile order: SCF_ORDER_STRIPS (all row chunks of a strip, then the next
+                             strip) or SCF_ORDER_BANDS (all strips of a row band, then the next
+                             band), optionally | SCF_ORDER_XCD (each of the 8 XCDs takes a
+                             contiguous eighth of that order instead of every 8th tile) */
+    int32_t graph_steps;  /* steps per captured HIP graph, 0 = launch every step directly */
+} scf_tile;
+
+enum { SCF_ORDER_STRIPS = 0, SCF_ORDER_BANDS = 1, SCF_ORDER_XCD = 2 };
+
 typedef struct scf_ctx scf_ctx;
 typedef struct scf_batch scf_batch;
 
@@ -122,16 +135,17 @@ int scf_get_populations(scf_ctx* ctx, double* f);
 /* Select the step kernel (SCF_VARIANT_*).  Default SCF_VARIANT_FUSED. */
 int scf_set_variant(scf_ctx* ctx, int32_t variant);
 
-/* Tile shape of the fused kernel: block width bx in {64, 128, 256} nodes along x and chunk
- * height cy >= 1 rows (cy >= ny: whole columns); graph_steps >= 0 steps per captured graph
- * (0 disables graphs).  Invalidates captured graphs.  Errors: SCF_EINVAL. */
-int scf_set_tile(scf_ctx* ctx, int32_t bx, int32_t cy, int32_t graph_steps);
+/* Set the launch schedule of the fused step: tiles of bx columns by cy rows (every other tile
+ * of a strip walks its rows downward), taken by the blocks of one launch in the given order.
+ * Schedules change only the order of work, never the result.
+ * Invalidates captured graphs.  Errors: SCF_EINVAL. */
+int scf_set_tile(scf_ctx* ctx, const scf_tile* tile);
+int scf_get_tile(const scf_ctx* ctx, scf_tile* tile);
 
-/* Time the candidate tile shapes on the current workspace for `trial_steps` steps each and
- * keep the fastest; the state is restored afterwards (the initial densities are re-applied
- * only if the context has not stepped yet, otherwise the current state is saved to host and
- * restored).  Writes the chosen bx, cy to *bx, *cy when non-NULL. */
-int scf_autotune(scf_ctx* ctx, int32_t trial_steps, int32_t* bx, int32_t* cy);
+/* Time candidate schedules (bx, cy, order) for `trial_steps` launches each and keep the
+ * fastest.  Every trial launch reads the resident buffer and writes the idle one, so the state
+ * is unchanged.  The graph length is kept.  Writes the chosen schedule to *chosen if non-NULL. */
+int scf_autotune(scf_ctx* ctx, int32_t trial_steps, scf_tile* chosen);
 
 /* Elapsed time step count of the context. */
 int64_t scf_time(const scf_ctx* ctx);
@@ -175,11 +189,12 @@ int scf_batch_observe(scf_batch* b, scf_obs* out, int64_t* nsamples);
 /* Host copy of channel c's densities (ny*nx FP64 each). */
 int scf_batch_get_density(scf_batch* b, int32_t c, double* nA, double* nB);
 
-/* Tile shape and graph length of the batched step, as scf_set_tile. */
-int scf_batch_set_tile(scf_batch* b, int32_t bx, int32_t cy, int32_t graph_steps);
+/* Schedule of the batched step, as scf_set_tile / scf_get_tile. */
+int scf_batch_set_tile(scf_batch* b, const scf_tile* tile);
+int scf_batch_get_tile(const scf_batch* b, scf_tile* tile);
 
-/* Autotune the batched step as scf_autotune (before the first scf_batch_step). */
-int scf_batch_autotune(scf_batch* b, int32_t trial_steps, int32_t* bx, int32_t* cy);
+/* Autotune the batched step as scf_autotune. */
+int scf_batch_autotune(scf_batch* b, int32_t trial_steps, scf_tile* chosen);
 
 void scf_batch_destroy(scf_batch* b);
 

@@ -39,6 +39,16 @@ class scf_obs(C.Structure):
                 "precursor_hi": self.precursor_hi, "flags": int(self.flags)}
 
 
+class scf_tile(C.Structure):
+    _fields_ = [("bx", C.c_int32), ("cy", C.c_int32), ("order", C.c_int32), ("graph_steps", C.c_int32)]
+
+    def as_dict(self) -> dict:
+        return {"bx": self.bx, "cy": self.cy, "order": self.order, "graph_steps": self.graph_steps}
+
+
+SCF_ORDER_STRIPS, SCF_ORDER_BANDS, SCF_ORDER_XCD = 0, 1, 2
+
+
 class ScfError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"{ERROR_NAMES.get(code, code)}: {msg}")
@@ -61,8 +71,9 @@ _sig = {
     "scf_get_density": (C.c_int, [_vp, _dp, _dp]),
     "scf_get_populations": (C.c_int, [_vp, _dp]),
     "scf_set_variant": (C.c_int, [_vp, C.c_int32]),
-    "scf_set_tile": (C.c_int, [_vp, C.c_int32, C.c_int32, C.c_int32]),
-    "scf_autotune": (C.c_int, [_vp, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
+    "scf_set_tile": (C.c_int, [_vp, C.POINTER(scf_tile)]),
+    "scf_get_tile": (C.c_int, [_vp, C.POINTER(scf_tile)]),
+    "scf_autotune": (C.c_int, [_vp, C.c_int32, C.POINTER(scf_tile)]),
     "scf_time": (C.c_int64, [_vp]),
     "scf_save": (C.c_int, [_vp, C.c_char_p]),
     "scf_load": (C.c_int, [_vp, C.c_char_p]),
@@ -75,8 +86,9 @@ _sig = {
     "scf_batch_step": (C.c_int, [_vp, C.c_int64]),
     "scf_batch_observe": (C.c_int, [_vp, C.POINTER(scf_obs), C.POINTER(C.c_int64)]),
     "scf_batch_get_density": (C.c_int, [_vp, C.c_int32, _dp, _dp]),
-    "scf_batch_set_tile": (C.c_int, [_vp, C.c_int32, C.c_int32, C.c_int32]),
-    "scf_batch_autotune": (C.c_int, [_vp, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
+    "scf_batch_set_tile": (C.c_int, [_vp, C.POINTER(scf_tile)]),
+    "scf_batch_get_tile": (C.c_int, [_vp, C.POINTER(scf_tile)]),
+    "scf_batch_autotune": (C.c_int, [_vp, C.c_int32, C.POINTER(scf_tile)]),
     "scf_batch_destroy": (None, [_vp]),
 }
 for _name, (_res, _args) in _sig.items():

@@ -51,6 +51,8 @@ struct ObsRec {
 
 struct TileDesc {
     int32_t chan, xb, yb, ye;   // strip [xb, xb+bx) x rows [yb, ye)
+    int32_t down;               // 0: rows walked upward from yb, 1: downward from ye-1
+    int32_t pad[3];
 };
 
 // Kernel launchers (all asynchronous on `stream`; return hipSuccess or the launch error).

@@ -67,6 +67,70 @@ __device__ __forceinline__ void pull_node(const float* __restrict__ g, const Cha
         pull18<false>(g, c, x, y, f);
 }
 
+// Buffer-descriptor access for the fused step: one descriptor per population buffer (18 planes,
+// at most 4 GiB, checked by the host), 32-bit byte offsets, plane offsets in scalar registers.
+constexpr int kBufferDword3 = 0x00020000;   // raw buffer, 32-bit data format (gfx9 family)
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const float* base, int64_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(base), 0, (int)bytes, kBufferDword3);
+}
+__device__ __forceinline__ float bload(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+
+// As pull18, through a buffer descriptor; Pb = plane size in bytes.
+template <bool WALLS>
+__device__ __forceinline__ void pull18_buf(__amdgpu_buffer_rsrc_t r, int Pb, const Chan& c, int x,
+                                           int y, float f[18]) {
+    const int xm = dec_wrap(x, c.nx), xp = inc_wrap(x, c.nx);
+    const int ym = dec_wrap(y, c.ny), yp = inc_wrap(y, c.ny);
+    const int sx[9] = {x, xm, x, xp, x, xm, xp, xp, xm};
+    const int sy[9] = {y, y, ym, y, yp, ym, ym, yp, yp};
+    const int opp[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        const int off = (sy[i] * c.pitch + sx[i]) * 4;
+        if (WALLS && i > 0) {
+            // bounce-back lanes read their own node's opposite direction: fold the plane into
+            // the per-lane offset so the scalar offset stays uniform
+            const bool sol = solid_at(c, sx[i], sy[i]);
+            const int o = sol ? (y * c.pitch + x) * 4 + opp[i] * Pb : off + i * Pb;
+            f[i] = bload(r, o, 0);
+            f[9 + i] = bload(r, o, 9 * Pb);
+        } else {
+            f[i] = bload(r, off, i * Pb);
+            f[9 + i] = bload(r, off, (9 + i) * Pb);
+        }
+    }
+}
+
+__device__ __forceinline__ void pull_node_buf(__amdgpu_buffer_rsrc_t r, int Pb, const Chan& c,
+                                              int x, int y, float f[18]) {
+    if (near_wall(c, y))
+        pull18_buf<true>(r, Pb, c, x, y, f);
+    else
+        pull18_buf<false>(r, Pb, c, x, y, f);
+}
+
+// Destinations of the post-collision populations: plain global stores or buffer stores, both
+// non-temporal (the values are not read again within the step).
+struct GlobalOut {
+    float* d;
+    int64_t P;
+    int idx;
+    __device__ __forceinline__ void operator()(int q, float v) const {
+        __builtin_nontemporal_store(v, &d[q * P + idx]);
+    }
+};
+struct BufferOut {
+    __amdgpu_buffer_rsrc_t r;
+    int Pb;
+    int off;
+    __device__ __forceinline__ void operator()(int q, float v) const {
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, off, q * Pb, 2);
+    }
+};
+
 __device__ __forceinline__ float sum9(const float* f) {
     float s = f[0];
 #pragma unroll
@@ -99,8 +163,9 @@ constexpr float kThirdLo = (float)(1.0 / 3.0 - (double)kThirdHi);
 
 __device__ __forceinline__ float third(float v) { return __builtin_fmaf(v, kThirdHi, v * kThirdLo); }
 
+template <class Out>
 __device__ __forceinline__ void relax_store(const float* f, float n, float ux, float uy, float c1,
-                                            float om, float* __restrict__ out, int64_t P, int idx) {
+                                            float om, const Out& out, int qbase) {
     const float usq6 = (ux * ux + uy * uy) * (1.0f / 6.0f);
     const float up = ux + uy, um = uy - ux;
     const float ox = third(ux), oy = third(uy), op = third(up), oq = third(um);
@@ -118,14 +183,15 @@ __device__ __forceinline__ void relax_store(const float* f, float n, float ux, f
     D[8] = (r4 - f[8]) + n4 * (eq - oq);
     D[0] = -(((D[1] + D[2]) + (D[3] + D[4])) + ((D[5] + D[6]) + (D[7] + D[8])));
 #pragma unroll
-    for (int i = 0; i < 9; ++i) out[i * P + idx] = f[i] + om * D[i];
+    for (int i = 0; i < 9; ++i) out(qbase + i, f[i] + om * D[i]);
 }
 
 // Collide one fluid node: f holds its pulled populations (A then B), nA/nB their sums,
 // sAx.. the weighted neighbour sums of n_A and n_B, swx/swy the weighted solid-neighbour sum.
+template <class Out>
 __device__ __forceinline__ void collide_store(const Chan& c, const float f[18], float nA, float nB,
                                               float sAx, float sAy, float sBx, float sBy, float swx,
-                                              float swy, float* __restrict__ d, int idx) {
+                                              float swy, const Out& out) {
     const float jAx = (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
     const float jAy = (f[2] - f[4]) + (f[5] - f[7]) + (f[6] - f[8]);
     const float jBx = (f[10] - f[12]) + (f[14] - f[15]) + (f[17] - f[16]);
@@ -136,39 +202,43 @@ __device__ __forceinline__ void collide_store(const Chan& c, const float f[18], 
     const float den = c.wm[0] * nA + c.wm[1] * nB;
     const float Ux = (c.wm[0] * jAx + c.wm[1] * jBx) / den;
     const float Uy = (c.wm[0] * jAy + c.wm[1] * jBy) / den;
-    const int64_t P = c.plane;
-    relax_store(f, nA, Ux + c.tm[0] * aAx, Uy + c.tm[0] * aAy, c.c1[0], c.omega[0], d, P, idx);
-    relax_store(f + 9, nB, Ux + c.tm[1] * aBx, Uy + c.tm[1] * aBy, c.c1[1], c.omega[1], d + 9 * P, P,
-                idx);
+    relax_store(f, nA, Ux + c.tm[0] * aAx, Uy + c.tm[0] * aAy, c.c1[0], c.omega[0], out, 0);
+    relax_store(f + 9, nB, Ux + c.tm[1] * aBx, Uy + c.tm[1] * aBy, c.c1[1], c.omega[1], out, 9);
 }
 
 // ---------------------------------------------------------------------------------------------
 // Fused step.  A block of BX threads owns a strip of BX columns and a chunk [yb, ye) of rows,
-// walked bottom to top.  Iteration `it` pulls row yb-1+it, writes its densities into a 4-slot
-// LDS ring (plus the two halo columns, pulled by lanes 0 and 1), and after one barrier collides
-// the row below it, whose populations were kept in registers from the previous iteration.
-// Rows yb-1 and ye are density-only halos.  A slot written at iteration it+1 was last read by
+// walked row by row, upward or downward.  Iteration `it` pulls one row, writes its densities
+// into a 4-slot LDS ring (plus the two halo columns, pulled by lanes 0 and 1), and after one
+// barrier collides the previous row, whose populations were kept in registers.  The first and
+// last rows pulled are density-only halos.  A slot written at iteration it+1 was last read by
 // the collision of iteration it-1, which every thread finished before the barrier of iteration
 // it, so one barrier per row suffices.
+//
+// Neighbouring chunks of a strip walk in opposite directions: all chunks start together, so
+// the rows two chunks share are then pulled by both at about the same time and the second
+// read hits in L2 instead of going back to HBM.
 // ---------------------------------------------------------------------------------------------
 template <int BX>
 __global__ void __launch_bounds__(BX)
 k_step_fused(const Chan* __restrict__ chans, const TileDesc* __restrict__ tiles, int ntiles,
-             int vtotal, float* __restrict__ ws, int src) {
+             float* __restrict__ ws, int src) {
     __shared__ float sn[2][4][BX + 2];
     const int tid = threadIdx.x;
-    const int per = vtotal >> 3;
-    for (int v = blockIdx.x; v < vtotal; v += gridDim.x) {
-        // consecutive tiles of the list go to the same XCD (blocks are dealt round-robin to 8)
-        const int t = (v & 7) * per + (v >> 3);
-        if (t >= ntiles) continue;
+    // Tiles are taken in list order; the host orders the list for the XCD placement it wants
+    // (blocks are dealt round-robin to the 8 XCDs).  Empty tiles pad such orders.
+    for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
         const TileDesc td = tiles[t];
+        if (td.ye <= td.yb) continue;
         const Chan c = chans[td.chan];
+        const bool down = td.down != 0;
         const int w = min(BX, c.nx - td.xb);
         const bool act = tid < w;
         const int x = td.xb + (act ? tid : w - 1);
-        const float* __restrict__ g = ws + c.off + (int64_t)src * 18 * c.plane;
-        float* __restrict__ d = ws + c.off + (int64_t)(src ^ 1) * 18 * c.plane;
+        const int64_t buf_bytes = (int64_t)18 * c.plane * 4;
+        const __amdgpu_buffer_rsrc_t rs = make_rsrc(ws + c.off + (int64_t)src * 18 * c.plane, buf_bytes);
+        const __amdgpu_buffer_rsrc_t rd = make_rsrc(ws + c.off + (int64_t)(src ^ 1) * 18 * c.plane, buf_bytes);
+        const int Pb = (int)(c.plane * 4);
         const bool walls = c.x1 > c.x0;
         const int hx = tid == 0 ? (td.xb == 0 ? c.nx - 1 : td.xb - 1)
                                 : (td.xb + w == c.nx ? 0 : td.xb + w);
@@ -177,12 +247,13 @@ k_step_fused(const Chan* __restrict__ chans, const TileDesc* __restrict__ tiles,
 #pragma unroll
         for (int i = 0; i < 18; ++i) q[i] = 0.0f;
         float qA = 0.0f, qB = 0.0f;
-        int y = td.yb == 0 ? c.ny - 1 : td.yb - 1;
+        // first row pulled: the halo below (upward walk) or above (downward walk) the chunk
+        int y = down ? (td.ye == c.ny ? 0 : td.ye) : (td.yb == 0 ? c.ny - 1 : td.yb - 1);
         const int niter = td.ye - td.yb + 2;
         for (int it = 0; it < niter; ++it) {
             const int slot = it & 3;
             float p[18];
-            pull_node(g, c, x, y, p);
+            pull_node_buf(rs, Pb, c, x, y, p);
             float nA = 0.0f, nB = 0.0f;
             if (!(walls && solid_at(c, x, y))) {
                 nA = sum9(p);
@@ -194,7 +265,7 @@ k_step_fused(const Chan* __restrict__ chans, const TileDesc* __restrict__ tiles,
             }
             if (tid < 2) {
                 float h[18];
-                pull_node(g, c, hx, y, h);
+                pull_node_buf(rs, Pb, c, hx, y, h);
                 float hA = 0.0f, hB = 0.0f;
                 if (!(walls && solid_at(c, hx, y))) {
                     hA = sum9(h);
@@ -205,9 +276,12 @@ k_step_fused(const Chan* __restrict__ chans, const TileDesc* __restrict__ tiles,
             }
             __syncthreads();
             if (it >= 2 && act) {
-                const int yc = y == 0 ? c.ny - 1 : y - 1;
+                // the row collided now was pulled one iteration ago
+                const int yc = down ? (y == c.ny - 1 ? 0 : y + 1) : (y == 0 ? c.ny - 1 : y - 1);
                 if (!(walls && solid_at(c, x, yc))) {
-                    const int sm = (it - 2) & 3, s0 = (it - 1) & 3, sp = slot;
+                    const int s0 = (it - 1) & 3;
+                    const int sm = down ? slot : (it - 2) & 3;   // row yc - 1
+                    const int sp = down ? (it - 2) & 3 : slot;   // row yc + 1
                     const int l = tid + 1;
                     const float AE = sn[0][s0][l + 1], AW = sn[0][s0][l - 1];
                     const float AN = sn[0][sp][l], AS = sn[0][sm][l];
@@ -223,14 +297,15 @@ k_step_fused(const Chan* __restrict__ chans, const TileDesc* __restrict__ tiles,
                     const float sBy = W1 * (BN - BS) + W2 * ((BNE - BSW) + (BNW - BSE));
                     float swx = 0.0f, swy = 0.0f;
                     if (near_wall(c, yc)) wall_sum(c, x, yc, swx, swy);
-                    collide_store(c, q, qA, qB, sAx, sAy, sBx, sBy, swx, swy, d, yc * c.pitch + x);
+                    collide_store(c, q, qA, qB, sAx, sAy, sBx, sBy, swx, swy,
+                                  BufferOut{rd, Pb, (yc * c.pitch + x) * 4});
                 }
             }
 #pragma unroll
             for (int i = 0; i < 18; ++i) q[i] = p[i];
             qA = nA;
             qB = nB;
-            y = y == c.ny - 1 ? 0 : y + 1;
+            y = down ? (y == 0 ? c.ny - 1 : y - 1) : (y == c.ny - 1 ? 0 : y + 1);
         }
         __syncthreads();
     }
@@ -292,7 +367,7 @@ k_collide(const Chan* __restrict__ chans, const RowRef* __restrict__ rows, float
         const float sBy = W1 * (BN - BS) + W2 * ((BNE - BSW) + (BNW - BSE));
         float swx = 0.0f, swy = 0.0f;
         if (near_wall(c, y)) wall_sum(c, x, y, swx, swy);
-        collide_store(c, p, nA, nB, sAx, sAy, sBx, sBy, swx, swy, d, r0 + x);
+        collide_store(c, p, nA, nB, sAx, sAy, sBx, sBy, swx, swy, GlobalOut{d, c.plane, r0 + x});
     }
 }
 
@@ -500,10 +575,8 @@ __global__ void k_bump(int32_t* counter) {
 template <int BX>
 hipError_t launch_fused_bx(const Chan* chans, const TileDesc* tiles, int ntiles, int grid,
                            float* ws, int src, hipStream_t s) {
-    const int vtotal = 8 * ((ntiles + 7) / 8);
-    const int g = grid > 0 ? min(grid, vtotal) : vtotal;
-    hipLaunchKernelGGL(k_step_fused<BX>, dim3(g), dim3(BX), 0, s, chans, tiles, ntiles, vtotal, ws,
-                       src);
+    const int g = grid > 0 ? min(grid, ntiles) : ntiles;
+    hipLaunchKernelGGL(k_step_fused<BX>, dim3(g), dim3(BX), 0, s, chans, tiles, ntiles, ws, src);
     return hipGetLastError();
 }
 

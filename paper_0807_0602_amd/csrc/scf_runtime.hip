@@ -50,8 +50,9 @@ bool geom_ok(const scf_geometry* g, std::string* why) {
         *why = "need 0 <= x0 <= x1 <= nx";
         return false;
     }
-    if ((int64_t)g->ny * pitch_of(g->nx) > (int64_t)std::numeric_limits<int32_t>::max()) {
-        *why = "ny * nx too large for one channel";
+    // one population buffer (18 planes of FP32) is addressed with 32-bit byte offsets
+    if ((int64_t)18 * 4 * g->ny * pitch_of(g->nx) >= (int64_t)std::numeric_limits<int32_t>::max()) {
+        *why = "ny * nx too large for one channel (18 planes must stay below 2 GiB)";
         return false;
     }
     return true;
@@ -76,7 +77,7 @@ struct Layout {
     int nrows = 0, max_tiles = 0;
 };
 
-int max_tiles_of(const scf_geometry& g) { return ((g.nx + 63) / 64) * g.ny; }
+int max_tiles_of(const scf_geometry& g) { return ((g.nx + 63) / 64) * g.ny; }   // bx = 64, cy = 1
 
 Layout plan(int nchan, const scf_geometry* g, int max_samples) {
     Layout L;
@@ -84,6 +85,7 @@ Layout plan(int nchan, const scf_geometry* g, int max_samples) {
     L.chans = off; off = align_up(off + sizeof(scf::Chan) * nchan, 256);
     for (int c = 0; c < nchan; ++c) { L.nrows += g[c].ny; L.max_tiles += max_tiles_of(g[c]); }
     L.rows = off; off = align_up(off + sizeof(scf::RowRef) * L.nrows, 256);
+    L.max_tiles += 8;   // padding of the XCD-contiguous order
     L.tiles = off; off = align_up(off + sizeof(scf::TileDesc) * L.max_tiles, 256);
     L.parts = off; off = align_up(off + sizeof(scf::RowPartial) * L.nrows, 256);
     L.now = off; off = align_up(off + sizeof(scf::ObsRec) * nchan, 256);
@@ -132,7 +134,7 @@ struct Engine {
     int cur = 0;
     int64_t t = 0;
     int variant = SCF_VARIANT_FUSED;
-    int bx = 256, cy = 64, graph_steps = 64, grid = 0;
+    int bx = 256, cy = 64, order = SCF_ORDER_STRIPS, graph_steps = 64, grid = 0;
     int ntiles = 0;
     hipGraphExec_t g_steps[2] = {nullptr, nullptr};
     hipGraphExec_t g_sample[2] = {nullptr, nullptr};
@@ -162,20 +164,49 @@ struct Engine {
         }
     }
 
-    std::vector<scf::TileDesc> make_tiles(int bxv, int cyv) const {
+    // Tiles of every channel in the requested order.  Within a strip, consecutive row chunks
+    // alternate direction (see k_step_fused).  Blocks take tiles in list order and are dealt
+    // round-robin to the 8 XCDs; with SCF_ORDER_XCD the list is permuted so that each XCD gets
+    // a contiguous eighth of the base order (empty tiles pad the last round).
+    std::vector<scf::TileDesc> make_tiles(int bxv, int cyv, int ord) const {
+        const bool bands = (ord & SCF_ORDER_BANDS) != 0;
         std::vector<scf::TileDesc> tl;
         for (int c = 0; c < nchan; ++c) {
             const scf_geometry& g = geom[c];
             const int chunk = std::min(cyv, g.ny);
-            for (int xb = 0; xb < g.nx; xb += bxv)
-                for (int yb = 0; yb < g.ny; yb += chunk)
-                    tl.push_back({c, xb, yb, std::min(yb + chunk, g.ny)});
+            const int nstrip = (g.nx + bxv - 1) / bxv;
+            const int nchunk = (g.ny + chunk - 1) / chunk;
+            for (int a = 0; a < (bands ? nchunk : nstrip); ++a)
+                for (int b = 0; b < (bands ? nstrip : nchunk); ++b) {
+                    const int s_ = bands ? b : a;
+                    const int k = bands ? a : b;
+                    scf::TileDesc td;
+                    std::memset(&td, 0, sizeof td);
+                    td.chan = c;
+                    td.xb = s_ * bxv;
+                    td.yb = k * chunk;
+                    td.ye = std::min(td.yb + chunk, g.ny);
+                    td.down = k & 1;
+                    tl.push_back(td);
+                }
         }
-        return tl;
+        if (!(ord & SCF_ORDER_XCD)) return tl;
+        const int n = (int)tl.size();
+        const int per = (n + 7) / 8;
+        std::vector<scf::TileDesc> out((size_t)per * 8);
+        for (int v = 0; v < per * 8; ++v) {
+            const int t = (v & 7) * per + (v >> 3);
+            if (t < n) {
+                out[v] = tl[t];
+            } else {
+                std::memset(&out[v], 0, sizeof out[v]);   // empty tile (ye == yb)
+            }
+        }
+        return out;
     }
 
-    int upload_tiles(int bxv, int cyv) {
-        std::vector<scf::TileDesc> tl = make_tiles(bxv, cyv);
+    int upload_tiles(int bxv, int cyv, int ord) {
+        std::vector<scf::TileDesc> tl = make_tiles(bxv, cyv, ord);
         if ((int)tl.size() > lay.max_tiles) return fail(SCF_EINVAL, "tile list exceeds its reserved space");
         HIP_TRY(hipMemcpyAsync(d_tiles(), tl.data(), sizeof(scf::TileDesc) * tl.size(),
                                hipMemcpyHostToDevice, stream));
@@ -183,6 +214,7 @@ struct Engine {
         ntiles = (int)tl.size();
         bx = bxv;
         cy = cyv;
+        order = ord;
         return SCF_OK;
     }
 
@@ -326,7 +358,7 @@ struct Engine {
         HIP_TRY(scf::launch_init(d_chans(), d_rows(), lay.nrows, base(), stream));
         cur = 0;
         t = 0;
-        int rc = upload_tiles(bx, cy);
+        int rc = upload_tiles(bx, cy, order);
         if (rc) return rc;
         if (sample_every > 0) {
             rc = observe_record();   // the t = 0 record
@@ -336,58 +368,67 @@ struct Engine {
         return SCF_OK;
     }
 
-    int set_tile(int bxv, int cyv, int gsteps) {
-        if (bxv != 64 && bxv != 128 && bxv != 256) return fail(SCF_EINVAL, "bx must be 64, 128 or 256");
-        if (cyv < 1) return fail(SCF_EINVAL, "cy must be >= 1");
-        if (gsteps < 0) return fail(SCF_EINVAL, "graph_steps must be >= 0");
+    int set_tile(const scf_tile* tl) {
+        if (!tl) return fail(SCF_EINVAL, "tile is NULL");
+        if (tl->bx != 64 && tl->bx != 128 && tl->bx != 256) return fail(SCF_EINVAL, "bx must be 64, 128 or 256");
+        if (tl->cy < 1) return fail(SCF_EINVAL, "cy must be >= 1");
+        if (tl->order < 0 || tl->order > (SCF_ORDER_BANDS | SCF_ORDER_XCD)) return fail(SCF_EINVAL, "unknown order");
+        if (tl->graph_steps < 0) return fail(SCF_EINVAL, "graph_steps must be >= 0");
         HIP_TRY(hipStreamSynchronize(stream));
         drop_graphs();
-        graph_steps = gsteps;
-        return upload_tiles(bxv, cyv);
+        graph_steps = tl->graph_steps;
+        return upload_tiles(tl->bx, tl->cy, tl->order);
+    }
+
+    void get_tile(scf_tile* tl) const {
+        tl->bx = bx;
+        tl->cy = cy;
+        tl->order = order;
+        tl->graph_steps = graph_steps;
     }
 
     // Time each candidate by repeated steps that all read the resident buffer and write the
     // idle one, so the state is never modified.
-    int autotune(int trial, int32_t* obx, int32_t* ocy) {
+    int autotune(int trial, scf_tile* chosen) {
         if (trial < 1) return fail(SCF_EINVAL, "trial_steps must be >= 1");
         HIP_TRY(hipStreamSynchronize(stream));
         int maxny = 0;
         for (auto& g : geom) maxny = std::max(maxny, g.ny);
         const int bxs[3] = {64, 128, 256};
-        const int cys[6] = {8, 16, 32, 64, 128, 1 << 30};
+        const int cys[8] = {4, 8, 16, 32, 48, 64, 128, 1 << 30};
         hipEvent_t e0, e1;
         HIP_TRY(hipEventCreate(&e0));
         HIP_TRY(hipEventCreate(&e1));
         float best = std::numeric_limits<float>::max();
-        int bbx = bx, bcy = cy;
+        int bbx = bx, bcy = cy, bord = order;
         const int saved_variant = variant;
         variant = SCF_VARIANT_FUSED;
         int rc = SCF_OK;
-        for (int bxv : bxs) {
-            for (int cyv : cys) {
-                if (cyv != (1 << 30) && cyv >= maxny) continue;
-                rc = upload_tiles(bxv, cyv);
+        for (int ord = 0; ord < 4 && !rc; ++ord)
+            for (int bxv : bxs) {
+                for (int cyv : cys) {
+                    if (cyv != (1 << 30) && cyv >= maxny) continue;
+                    rc = upload_tiles(bxv, cyv, ord);
+                    if (rc) break;
+                    for (int i = 0; i < 2; ++i) (void)launch_step(stream, cur);
+                    (void)hipEventRecord(e0, stream);
+                    for (int i = 0; i < trial; ++i) (void)launch_step(stream, cur);
+                    (void)hipEventRecord(e1, stream);
+                    if (hipEventSynchronize(e1) != hipSuccess) { rc = fail(SCF_EDEVICE, "autotune timing failed"); break; }
+                    float ms = 0.0f;
+                    (void)hipEventElapsedTime(&ms, e0, e1);
+                    if (ms < best) { best = ms; bbx = bxv; bcy = cyv; bord = ord; }
+                }
                 if (rc) break;
-                for (int i = 0; i < 2; ++i) (void)launch_step(stream, cur);
-                (void)hipEventRecord(e0, stream);
-                for (int i = 0; i < trial; ++i) (void)launch_step(stream, cur);
-                (void)hipEventRecord(e1, stream);
-                if (hipEventSynchronize(e1) != hipSuccess) { rc = fail(SCF_EDEVICE, "autotune timing failed"); break; }
-                float ms = 0.0f;
-                (void)hipEventElapsedTime(&ms, e0, e1);
-                if (ms < best) { best = ms; bbx = bxv; bcy = cyv; }
             }
-            if (rc) break;
-        }
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
         variant = saved_variant;
         if (rc) return rc;
         drop_graphs();
-        rc = upload_tiles(bbx, bcy);
+        rc = upload_tiles(bbx, bcy, bord);
         if (rc) return rc;
-        if (obx) *obx = bbx;
-        if (ocy) *ocy = bcy;
+        if (chosen) get_tile(chosen);
         return SCF_OK;
     }
 
@@ -488,14 +529,20 @@ int scf_set_variant(scf_ctx* ctx, int32_t variant) {
     return SCF_OK;
 }
 
-int scf_set_tile(scf_ctx* ctx, int32_t bx, int32_t cy, int32_t graph_steps) {
+int scf_set_tile(scf_ctx* ctx, const scf_tile* tile) {
     if (!ctx) return fail(SCF_EINVAL, "NULL context");
-    return ctx->e.set_tile(bx, cy, graph_steps);
+    return ctx->e.set_tile(tile);
 }
 
-int scf_autotune(scf_ctx* ctx, int32_t trial_steps, int32_t* bx, int32_t* cy) {
+int scf_get_tile(const scf_ctx* ctx, scf_tile* tile) {
+    if (!ctx || !tile) return fail(SCF_EINVAL, "NULL argument");
+    ctx->e.get_tile(tile);
+    return SCF_OK;
+}
+
+int scf_autotune(scf_ctx* ctx, int32_t trial_steps, scf_tile* chosen) {
     if (!ctx) return fail(SCF_EINVAL, "NULL context");
-    return ctx->e.autotune(trial_steps, bx, cy);
+    return ctx->e.autotune(trial_steps, chosen);
 }
 
 int64_t scf_time(const scf_ctx* ctx) { return ctx ? ctx->e.t : -1; }
@@ -627,14 +674,20 @@ int scf_batch_get_density(scf_batch* b, int32_t c, double* nA, double* nB) {
     return b->e.get_density(c, nA, nB);
 }
 
-int scf_batch_set_tile(scf_batch* b, int32_t bx, int32_t cy, int32_t graph_steps) {
+int scf_batch_set_tile(scf_batch* b, const scf_tile* tile) {
     if (!b) return fail(SCF_EINVAL, "NULL batch");
-    return b->e.set_tile(bx, cy, graph_steps);
+    return b->e.set_tile(tile);
 }
 
-int scf_batch_autotune(scf_batch* b, int32_t trial_steps, int32_t* bx, int32_t* cy) {
+int scf_batch_get_tile(const scf_batch* b, scf_tile* tile) {
+    if (!b || !tile) return fail(SCF_EINVAL, "NULL argument");
+    b->e.get_tile(tile);
+    return SCF_OK;
+}
+
+int scf_batch_autotune(scf_batch* b, int32_t trial_steps, scf_tile* chosen) {
     if (!b) return fail(SCF_EINVAL, "NULL batch");
-    return b->e.autotune(trial_steps, bx, cy);
+    return b->e.autotune(trial_steps, chosen);
 }
 
 void scf_batch_destroy(scf_batch* b) {

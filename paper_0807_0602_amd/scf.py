@@ -72,9 +72,10 @@ class Channel:
         return cls(case.geom, case.params, *case.fields(), **kw)
 
     def close(self) -> None:
-        if getattr(self, "_h", None):
+        # at interpreter shutdown the binding may already be torn down
+        if getattr(self, "_h", None) and getattr(L, "scf_destroy", None) is not None:
             L.scf_destroy(self._h)
-            self._h = None
+        self._h = None
 
     def __del__(self):
         self.close()
@@ -106,13 +107,19 @@ class Channel:
     def set_variant(self, variant: int) -> None:
         L.check(L.scf_set_variant(self._h, int(variant)))
 
-    def set_tile(self, bx: int, cy: int, graph_steps: int = 64) -> None:
-        L.check(L.scf_set_tile(self._h, int(bx), int(cy), int(graph_steps)))
+    def set_tile(self, bx: int, cy: int, graph_steps: int = 64, order: int = 0) -> None:
+        t = L.scf_tile(int(bx), int(cy), int(order), int(graph_steps))
+        L.check(L.scf_set_tile(self._h, C.byref(t)))
 
-    def autotune(self, trial_steps: int = 20) -> Tuple[int, int]:
-        bx, cy = C.c_int32(), C.c_int32()
-        L.check(L.scf_autotune(self._h, int(trial_steps), C.byref(bx), C.byref(cy)))
-        return bx.value, cy.value
+    def tile(self) -> dict:
+        t = L.scf_tile()
+        L.check(L.scf_get_tile(self._h, C.byref(t)))
+        return t.as_dict()
+
+    def autotune(self, trial_steps: int = 20) -> dict:
+        t = L.scf_tile()
+        L.check(L.scf_autotune(self._h, int(trial_steps), C.byref(t)))
+        return t.as_dict()
 
     def save(self, path: str) -> None:
         L.check(L.scf_save(self._h, path.encode()))
@@ -148,9 +155,9 @@ class Batch:
         self._h = h
 
     def close(self) -> None:
-        if getattr(self, "_h", None):
+        if getattr(self, "_h", None) and getattr(L, "scf_batch_destroy", None) is not None:
             L.scf_batch_destroy(self._h)
-            self._h = None
+        self._h = None
 
     def __del__(self):
         self.close()
@@ -175,10 +182,16 @@ class Batch:
         L.check(L.scf_batch_get_density(self._h, int(c), _dptr(a), _dptr(b)))
         return a, b
 
-    def set_tile(self, bx: int, cy: int, graph_steps: int = 64) -> None:
-        L.check(L.scf_batch_set_tile(self._h, int(bx), int(cy), int(graph_steps)))
+    def set_tile(self, bx: int, cy: int, graph_steps: int = 64, order: int = 0) -> None:
+        t = L.scf_tile(int(bx), int(cy), int(order), int(graph_steps))
+        L.check(L.scf_batch_set_tile(self._h, C.byref(t)))
 
-    def autotune(self, trial_steps: int = 10) -> Tuple[int, int]:
-        bx, cy = C.c_int32(), C.c_int32()
-        L.check(L.scf_batch_autotune(self._h, int(trial_steps), C.byref(bx), C.byref(cy)))
-        return bx.value, cy.value
+    def tile(self) -> dict:
+        t = L.scf_tile()
+        L.check(L.scf_batch_get_tile(self._h, C.byref(t)))
+        return t.as_dict()
+
+    def autotune(self, trial_steps: int = 10) -> dict:
+        t = L.scf_tile()
+        L.check(L.scf_batch_autotune(self._h, int(trial_steps), C.byref(t)))
+        return t.as_dict()

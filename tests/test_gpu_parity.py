@@ -123,14 +123,16 @@ def _state(ch):
     return ch.populations()
 
 
-@pytest.mark.parametrize("bx,cy", [(64, 8), (64, 1 << 30), (128, 5), (256, 64), (256, 1), (128, 23)])
-def test_tile_shapes_bitwise(scf, bx, cy):
+@pytest.mark.parametrize("bx,cy,order", [(64, 8, 0), (64, 1 << 30, 0), (128, 5, 0), (256, 64, 0),
+                                         (256, 1, 0), (128, 23, 0), (64, 4, 1), (256, 7, 1), (128, 1, 1),
+                                         (64, 3, 2), (256, 16, 3), (128, 1, 3)])
+def test_tile_shapes_bitwise(scf, bx, cy, order):
     case = inputs.capillary_small(seed=2)
-    _say(f"case: tile shape bx={bx} cy={cy}")
+    _say(f"case: tile shape bx={bx} cy={cy} order={order}")
     a = scf.Channel.from_case(case)
     a.step(120)
     b = scf.Channel.from_case(case)
-    b.set_tile(bx, cy, 64)
+    b.set_tile(bx, cy, 64, order)
     b.step(120)
     assert np.array_equal(_state(a), _state(b))
 
