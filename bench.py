@@ -12,6 +12,13 @@ once and written once).
 Prints ONE JSON line.  Options: --steps K (timed), --warmup W, --gpus N (only 1 is supported),
 --variant fused|two_kernel, --no-cpu-baseline, --calibrate-copy (runs only a plain copy kernel,
 for counter calibration under rocprofv3), --tile BX CY ORDER (skip the autotuner).
+
+--workload sweep measures the batched calibration sweep instead: 64 channels with H in
+{20, 40, 80, 160}, L in {512, ..., 4096}, G_wA uniform in [-0.3, 0.3] (G_wB = -G_wA) and a
+viscosity-ratio tau pair, advanced together (one launch per step over all their tiles, HIP
+graphs of 100 steps plus the recorded observation), 50 000 steps with z(t) and the precursor
+recorded every 100 steps.  The value is sweep points per hour (one point = one channel's whole
+trajectory).
 """
 from __future__ import annotations
 
@@ -37,9 +44,9 @@ def kernel_hash() -> str:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def measured_traffic(cells: int):
-    """HBM bytes per launch of the fused step from the committed counter summary, or None if
-    the kernel source changed since the counters were taken."""
+def measured_traffic(cells: int, schedule: dict):
+    """HBM bytes per launch of the fused step from the committed counter summary for this
+    schedule, or None if the kernel source changed since the counters were taken."""
     try:
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
@@ -47,7 +54,53 @@ def measured_traffic(cells: int):
         return None
     if t.get("kernel_sha256_16") != kernel_hash() or t.get("cells") != cells:
         return None
-    return t.get("bytes_per_launch")
+    for e in t.get("schedules", []):
+        if all(e["schedule"].get(k) == schedule.get(k) for k in ("bx", "cy", "order")):
+            return e["bytes_per_launch"]
+    return None
+
+
+def _counter_mean(path: str, kernel: str, counter: str) -> float:
+    import csv
+    vals = [float(r["Counter_Value"]) for r in csv.DictReader(open(path))
+            if kernel in r["Kernel_Name"] and r["Counter_Name"] == counter]
+    if not vals:
+        raise SystemExit(f"no {counter} rows for {kernel} in {path}")
+    return sum(vals) / len(vals)
+
+
+def summarize_counters(args) -> int:
+    """Fold rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE CSVs of the fused step and of the 1 GiB
+    calibration copy into TRAFFIC_FILE (one entry per schedule).  Each counter is scaled by
+    (bytes the copy kernel moves) / (what the counter reads for it)."""
+    fetch, write, fetch_copy, write_copy = args.summarize_counters
+    bx, cy, order = args.tile
+    copy_kib = (1 << 30) / 1024.0
+    f_scale = copy_kib / _counter_mean(fetch_copy, "copyBuffer", "FETCH_SIZE")
+    w_scale = copy_kib / _counter_mean(write_copy, "copyBuffer", "WRITE_SIZE")
+    rd = _counter_mean(fetch, "k_step_fused", "FETCH_SIZE") * f_scale * 1024.0
+    wr = _counter_mean(write, "k_step_fused", "WRITE_SIZE") * w_scale * 1024.0
+    from paper_0807_0602_amd import inputs
+    case = inputs.capillary_roofline(seed=1)
+    cells = case.geom.nx * case.geom.ny
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        t = {}
+    if t.get("kernel_sha256_16") != kernel_hash() or t.get("cells") != cells:
+        t = {"kernel": "k_step_fused", "workload": case.name, "cells": cells,
+             "kernel_sha256_16": kernel_hash(), "schedules": []}
+    sched = {"bx": bx, "cy": cy, "order": order}
+    t["schedules"] = [e for e in t["schedules"] if e["schedule"] != sched]
+    t["schedules"].append({"schedule": sched, "read_bytes_per_launch": round(rd),
+                           "write_bytes_per_launch": round(wr), "bytes_per_launch": round(rd + wr),
+                           "read_bytes_per_node": round(rd / cells, 2), "write_bytes_per_node": round(wr / cells, 2),
+                           "fetch_scale": round(f_scale, 4), "write_scale": round(w_scale, 4)})
+    with open(TRAFFIC_FILE, "w") as f:
+        json.dump(t, f, indent=1)
+    print(json.dumps(t["schedules"][-1]))
+    return 0
 
 
 def cpu_baseline(case, budget_s: float = 12.0, max_steps: int = 40) -> dict:
@@ -81,6 +134,57 @@ def calibrate_copy(nbytes: int = 1 << 30, reps: int = 5) -> None:
     print(json.dumps({"calibrate_copy_bytes": nbytes, "reps": reps}), flush=True)
 
 
+def sweep(args) -> int:
+    import torch
+    from paper_0807_0602_amd import inputs
+    from paper_0807_0602_amd.scf import Batch
+
+    steps = args.steps if args.steps != 10000 else 50_000
+    every = 100
+    cases = inputs.sweep_draws(64, seed=0, steps=steps, sample_every=every)
+    cells = sum(c.geom.nx * c.geom.ny for c in cases)
+    stream = torch.cuda.current_stream()
+    b = Batch(cases, sample_every=every, max_samples=steps // every + 1, stream=stream)
+    if args.tile:
+        b.set_tile(args.tile[0], args.tile[1], every, args.tile[2])
+    else:
+        b.autotune(5)
+        t = b.tile()
+        b.set_tile(t["bx"], t["cy"], every, t["order"])
+    tile = b.tile()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(stream)
+    b.step(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    recs, ns = b.observe(allow_unstable=True)
+    unstable = sum(1 for r in recs if any(x["flags"] & 2 for x in r))
+    step_s = e0.elapsed_time(e1) / 1e3 / steps
+    achieved = 144 * cells / step_s / 1e9
+    line = {
+        "metric": "calibration-sweep points/hour, batched LBM (one point = one channel trajectory)",
+        "value": round(len(cases) * 3600.0 / wall, 1), "unit": "points/h", "n_gpus": 1,
+        "stable_points_per_hour": round((len(cases) - unstable) * 3600.0 / wall, 1),
+        "steps": steps, "warmup": 0, "ms_per_step": round(wall * 1e3 / steps, 5),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "sweep_64_channels", "channels": len(cases), "nodes": cells,
+                   "sample_every": every, "samples_recorded": ns, "schedule": tile,
+                   "aggregate_mlups": round(cells * steps / wall / 1e6, 1),
+                   "unstable_channels": unstable},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "k_step_fused (all channels per launch) + observation every 100 steps",
+                     "bytes_per_node_update": 144},
+    }
+    print(json.dumps(line), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -90,7 +194,15 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true")
     ap.add_argument("--tile", type=int, nargs=3, default=None, metavar=("BX", "CY", "ORDER"))
+    ap.add_argument("--workload", choices=["roofline", "sweep"], default="roofline")
+    ap.add_argument("--summarize-counters", nargs=4, default=None,
+                    metavar=("FETCH_CSV", "WRITE_CSV", "FETCH_COPY_CSV", "WRITE_COPY_CSV"),
+                    help="write the traffic summary for the schedule given by --tile and exit")
     args = ap.parse_args()
+    if args.summarize_counters:
+        if not args.tile:
+            raise SystemExit("--summarize-counters needs --tile BX CY ORDER")
+        return summarize_counters(args)
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU; multi-GPU runs are not part of this build "
               "(the channel would be split into x-slabs with a halo exchange per step).",
@@ -101,6 +213,8 @@ def main() -> int:
     if args.calibrate_copy:
         calibrate_copy()
         return 0
+    if args.workload == "sweep":
+        return sweep(args)
 
     from paper_0807_0602_amd import _lib as L
     from paper_0807_0602_amd import inputs
@@ -137,7 +251,7 @@ def main() -> int:
     step_s = ev_ms / 1e3 / args.steps          # one kernel launch per fused step
     bpl = BYTES_PER_LUP[args.variant]
     achieved = bpl * cells / step_s / 1e9
-    traffic = measured_traffic(cells) if args.variant == "fused" else None
+    traffic = measured_traffic(cells, tile) if args.variant == "fused" else None
     line = {
         "metric": METRIC, "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(wall * 1e3 / args.steps, 5),
