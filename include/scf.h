@@ -198,6 +198,69 @@ int scf_batch_autotune(scf_batch* b, int32_t trial_steps, scf_tile* chosen);
 
 void scf_batch_destroy(scf_batch* b);
 
+/* ---------------------------------------------------------------------------------------------
+ * Surrogate: a multilayer perceptron that maps sweep parameters and time to the front and
+ * precursor positions, trained on trajectories of the batched LBM and used in its place inside
+ * the training range.  d_in inputs -> `depth` hidden SiLU layers of `width` units -> 2 outputs.
+ * Hidden-to-hidden layers run on BF16 MFMA with FP32 accumulation (forward and backward); the
+ * first and output layers, master weights, gradients and Adam moments are FP32.
+ * Inputs are normalised on the device by the mean and standard deviation of the data given to
+ * scf_sur_set_data (identity before any data).  Loss: (1/2n) sum_rows w_row |y - t|^2.
+ * Parameters are one FP32 vector, layer by layer: W (rows = outputs, row-major), then b.
+ * ------------------------------------------------------------------------------------------- */
+
+typedef struct scf_sur scf_sur;
+
+typedef struct {
+    int32_t d_in;        /* inputs per row, 1..32 */
+    int32_t width;       /* hidden units per layer, a positive multiple of 64 */
+    int32_t depth;       /* hidden layers, 1..16 */
+    int32_t max_batch;   /* rows per pass, a positive multiple of 64 */
+    int64_t max_data;    /* training rows the workspace holds */
+    float lr, beta1, beta2, eps;   /* Adam */
+    uint64_t seed;       /* parameter initialisation and minibatch draws */
+} scf_sur_cfg;
+
+/* Device workspace for a configuration; 0 if the configuration is invalid. */
+size_t scf_sur_workspace_bytes(const scf_sur_cfg* cfg);
+
+/* Create a network; weights are drawn on the device uniform in +-1/sqrt(fan_in) from cfg->seed,
+ * biases are 0, Adam moments 0.  Workspace and stream as for scf_init.  Synchronises. */
+int scf_sur_create(scf_sur** out, const scf_sur_cfg* cfg, void* dev_ws, size_t ws_bytes,
+                   void* hip_stream);
+
+/* Number of FP32 parameters (199 170 for 4 inputs, 256 x 4 hidden). */
+int64_t scf_sur_param_count(const scf_sur* s);
+int scf_sur_get_params(scf_sur* s, float* out);        /* host copy, param_count floats */
+int scf_sur_set_params(scf_sur* s, const float* in);   /* also refreshes the BF16 copies */
+int scf_sur_reset_optimizer(scf_sur* s);               /* Adam moments and step count to 0 */
+
+/* Copy n training rows (host: X n*d_in, T n*2, optional per-row weights w, NULL = 1) to the
+ * device and compute there the per-input mean, standard deviation, min and max (the training
+ * hull).  Errors: SCF_EINVAL (n outside [1, max_data]). */
+int scf_sur_set_data(scf_sur* s, const float* X, const float* T, const float* w, int64_t n);
+int scf_sur_get_norm(scf_sur* s, float* mean, float* stdv, float* lo, float* hi);   /* any may be NULL */
+
+/* One forward and backward pass on an explicit batch (n <= max_batch rows, host arrays):
+ * returns the loss and, if grad is non-NULL, the gradient (param_count floats). */
+int scf_sur_grad(scf_sur* s, const float* X, const float* T, const float* w, int32_t n,
+                 float* loss, float* grad);
+/* The same pass followed by one Adam update. */
+int scf_sur_step(scf_sur* s, const float* X, const float* T, const float* w, int32_t n,
+                 float* loss);
+
+/* `steps` Adam updates on minibatches of `batch` rows (a multiple of 64) drawn with replacement
+ * from the stored data by a counter-based hash; each update is one replay of a captured HIP
+ * graph.  Writes the last minibatch loss.  Errors: SCF_ESTATE without data. */
+int scf_sur_train(scf_sur* s, int64_t steps, int32_t batch, float* last_loss);
+
+/* Predictions for n rows (host X n*d_in -> Y n*2).  in_hull (optional, n bytes) is 1 where every
+ * input lies inside [min, max] of the stored training inputs; callers answer the other rows with
+ * the LBM. */
+int scf_sur_predict(scf_sur* s, const float* X, int64_t n, float* Y, uint8_t* in_hull);
+
+void scf_sur_destroy(scf_sur* s);
+
 #ifdef __cplusplus
 }
 #endif

@@ -49,6 +49,12 @@ class scf_tile(C.Structure):
 SCF_ORDER_STRIPS, SCF_ORDER_BANDS, SCF_ORDER_XCD = 0, 1, 2
 
 
+class scf_sur_cfg(C.Structure):
+    _fields_ = [("d_in", C.c_int32), ("width", C.c_int32), ("depth", C.c_int32), ("max_batch", C.c_int32),
+                ("max_data", C.c_int64), ("lr", C.c_float), ("beta1", C.c_float), ("beta2", C.c_float),
+                ("eps", C.c_float), ("seed", C.c_uint64)]
+
+
 class ScfError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"{ERROR_NAMES.get(code, code)}: {msg}")
@@ -62,6 +68,7 @@ lib = C.CDLL(LIB_PATH)
 
 _vp = C.c_void_p
 _dp = C.POINTER(C.c_double)
+_fp = C.POINTER(C.c_float)
 _sig = {
     "scf_workspace_bytes": (C.c_size_t, [C.POINTER(scf_geometry)]),
     "scf_init": (C.c_int, [C.POINTER(_vp), C.POINTER(scf_geometry), C.POINTER(scf_params), _dp, _dp,
@@ -90,6 +97,19 @@ _sig = {
     "scf_batch_get_tile": (C.c_int, [_vp, C.POINTER(scf_tile)]),
     "scf_batch_autotune": (C.c_int, [_vp, C.c_int32, C.POINTER(scf_tile)]),
     "scf_batch_destroy": (None, [_vp]),
+    "scf_sur_workspace_bytes": (C.c_size_t, [C.POINTER(scf_sur_cfg)]),
+    "scf_sur_create": (C.c_int, [C.POINTER(_vp), C.POINTER(scf_sur_cfg), _vp, C.c_size_t, _vp]),
+    "scf_sur_param_count": (C.c_int64, [_vp]),
+    "scf_sur_get_params": (C.c_int, [_vp, _fp]),
+    "scf_sur_set_params": (C.c_int, [_vp, _fp]),
+    "scf_sur_reset_optimizer": (C.c_int, [_vp]),
+    "scf_sur_set_data": (C.c_int, [_vp, _fp, _fp, _fp, C.c_int64]),
+    "scf_sur_get_norm": (C.c_int, [_vp, _fp, _fp, _fp, _fp]),
+    "scf_sur_grad": (C.c_int, [_vp, _fp, _fp, _fp, C.c_int32, _fp, _fp]),
+    "scf_sur_step": (C.c_int, [_vp, _fp, _fp, _fp, C.c_int32, _fp]),
+    "scf_sur_train": (C.c_int, [_vp, C.c_int64, C.c_int32, _fp]),
+    "scf_sur_predict": (C.c_int, [_vp, _fp, C.c_int64, _fp, C.POINTER(C.c_uint8)]),
+    "scf_sur_destroy": (None, [_vp]),
 }
 for _name, (_res, _args) in _sig.items():
     _f = getattr(lib, _name)

@@ -9,7 +9,8 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libscf.so")
-SOURCES = [os.path.join(CSRC, f) for f in ("scf_kernels.hip", "scf_runtime.hip")]
+SOURCES = [os.path.join(CSRC, f) for f in ("scf_kernels.hip", "scf_runtime.hip", "sur_kernels.hip",
+                                          "sur_runtime.hip")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 

@@ -121,6 +121,11 @@ scf::Chan make_chan(const scf_geometry& g, const scf_params& p, size_t byte_off,
 
 }  // namespace
 
+namespace scf {
+// Error reporting shared with the surrogate runtime.
+int set_error(int code, const std::string& msg) { return fail(code, msg); }
+}  // namespace scf
+
 struct Engine {
     int nchan = 0;
     std::vector<scf_geometry> geom;
