@@ -240,6 +240,9 @@ int scf_sur_reset_optimizer(scf_sur* s);               /* Adam moments and step 
  * hull).  Errors: SCF_EINVAL (n outside [1, max_data]). */
 int scf_sur_set_data(scf_sur* s, const float* X, const float* T, const float* w, int64_t n);
 int scf_sur_get_norm(scf_sur* s, float* mean, float* stdv, float* lo, float* hi);   /* any may be NULL */
+/* Set the input normalisation and the training hull directly (d_in floats each, stdv > 0), e.g.
+ * for a network whose parameters were saved after training.  Errors: SCF_EINVAL. */
+int scf_sur_set_norm(scf_sur* s, const float* mean, const float* stdv, const float* lo, const float* hi);
 
 /* One forward and backward pass on an explicit batch (n <= max_batch rows, host arrays):
  * returns the loss and, if grad is non-NULL, the gradient (param_count floats). */

@@ -105,6 +105,7 @@ _sig = {
     "scf_sur_reset_optimizer": (C.c_int, [_vp]),
     "scf_sur_set_data": (C.c_int, [_vp, _fp, _fp, _fp, C.c_int64]),
     "scf_sur_get_norm": (C.c_int, [_vp, _fp, _fp, _fp, _fp]),
+    "scf_sur_set_norm": (C.c_int, [_vp, _fp, _fp, _fp, _fp]),
     "scf_sur_grad": (C.c_int, [_vp, _fp, _fp, _fp, C.c_int32, _fp, _fp]),
     "scf_sur_step": (C.c_int, [_vp, _fp, _fp, _fp, C.c_int32, _fp]),
     "scf_sur_train": (C.c_int, [_vp, C.c_int64, C.c_int32, _fp]),

@@ -308,6 +308,20 @@ int scf_sur_get_norm(scf_sur* s, float* mean, float* stdv, float* lo, float* hi)
     return SCF_OK;
 }
 
+int scf_sur_set_norm(scf_sur* s, const float* mean, const float* stdv, const float* lo, const float* hi) {
+    if (!s || !mean || !stdv || !lo || !hi) return set_error(SCF_EINVAL, "NULL argument");
+    for (int k = 0; k < s->cfg.d_in; ++k)
+        if (!(stdv[k] > 0.0f)) return set_error(SCF_EINVAL, "stdv must be > 0");
+    const size_t nb = sizeof(float) * s->cfg.d_in;
+    SUR_TRY(hipMemcpyAsync(s->at<float>(s->p.mean), mean, nb, hipMemcpyHostToDevice, s->stream));
+    SUR_TRY(hipMemcpyAsync(s->at<float>(s->p.stdv), stdv, nb, hipMemcpyHostToDevice, s->stream));
+    SUR_TRY(hipMemcpyAsync(s->at<float>(s->p.lo), lo, nb, hipMemcpyHostToDevice, s->stream));
+    SUR_TRY(hipMemcpyAsync(s->at<float>(s->p.hi), hi, nb, hipMemcpyHostToDevice, s->stream));
+    SUR_TRY(hipStreamSynchronize(s->stream));
+    s->have_stats = true;
+    return SCF_OK;
+}
+
 int scf_sur_grad(scf_sur* s, const float* X, const float* T, const float* w, int32_t n, float* loss, float* grad) {
     if (!s || !X || !T) return set_error(SCF_EINVAL, "NULL argument");
     int rows = 0;

@@ -88,6 +88,24 @@ class Network:
         L.check(L.scf_sur_get_norm(self._h, _fp(out["mean"]), _fp(out["std"]), _fp(out["lo"]), _fp(out["hi"])))
         return out
 
+    def set_norm(self, mean, std, lo, hi) -> None:
+        a = [np.ascontiguousarray(v, np.float32) for v in (mean, std, lo, hi)]
+        L.check(L.scf_sur_set_norm(self._h, *[_fp(v) for v in a]))
+
+    def save(self, path: str, **extra) -> None:
+        n = self.norm()
+        c = self.cfg
+        np.savez(path, theta=self.params(), mean=n["mean"], std=n["std"], lo=n["lo"], hi=n["hi"],
+                 d_in=c.d_in, width=c.width, depth=c.depth, **extra)
+
+    @classmethod
+    def load(cls, path: str, max_batch: int = 4096, **kw) -> "Network":
+        z = np.load(path)
+        net = cls(int(z["d_in"]), int(z["width"]), int(z["depth"]), max_batch=max_batch, max_data=64, **kw)
+        net.set_params(z["theta"])
+        net.set_norm(z["mean"], z["std"], z["lo"], z["hi"])
+        return net
+
     def grad(self, X, T, w=None) -> Tuple[float, np.ndarray]:
         X = np.ascontiguousarray(X, np.float32); T = np.ascontiguousarray(T, np.float32)
         wp = None
@@ -117,3 +135,209 @@ class Network:
         Y = np.empty((n, 2), np.float32); inside = np.empty(n, np.uint8)
         L.check(L.scf_sur_predict(self._h, _fp(X), n, _fp(Y), inside.ctypes.data_as(C.POINTER(C.c_uint8))))
         return Y, inside.astype(bool)
+
+
+# ---------------------------------------------------------------------------------------------
+# Data from the batched LBM, training, evaluation and the LBM fallback.
+# ---------------------------------------------------------------------------------------------
+
+RATIOS = (1, 2, 5, 10)
+
+
+def draw_cases(n: int, seed: int, steps: int = 50_000, every: int = 100) -> List[Case]:
+    """n channels with G_wA ~ U[-0.3, 0.3], H ~ U{20..160}, L ~ U{512..4096} in multiples of 4
+    and r uniform over {1, 2, 5, 10} (tau pair per the working map of inputs.TAU_FOR_RATIO)."""
+    from .inputs import sweep_channel
+    rng = np.random.default_rng(seed)
+    out = []
+    for c in range(n):
+        H = int(rng.integers(20, 161))
+        L_ = 4 * int(rng.integers(128, 1025))
+        r = int(rng.choice(RATIOS))
+        g = float(rng.uniform(-0.3, 0.3))
+        out.append(sweep_channel(H, L_, g, r, seed=100_000 * (seed + 1) + c, steps=steps, sample_every=every))
+    return out
+
+
+def simulate(cases: Sequence[Case], steps: int, every: int, group: int = 64, log=None) -> np.ndarray:
+    """Trajectories of every channel from the batched LBM, `group` channels per batch.
+    Returns float64 [n, steps/every + 1, 5]: t, z, precursor, flags, unstable-so-far."""
+    from .scf import Batch
+    ns = steps // every + 1
+    out = np.full((len(cases), ns, 5), np.nan)
+    for g0 in range(0, len(cases), group):
+        part = list(cases[g0:g0 + group])
+        b = Batch(part, sample_every=every, max_samples=ns)
+        t = b.tile()
+        b.set_tile(t["bx"], 8, every, 1)
+        b.step(steps)
+        recs, k = b.observe(allow_unstable=True)
+        for c, r in enumerate(recs):
+            bad = False
+            for s, x in enumerate(r):
+                bad = bad or bool(x["flags"] & 2)
+                out[g0 + c, s] = (x["t"], x["z"], x["precursor"], x["flags"], float(bad))
+        b.close()
+        if log:
+            log(f"simulated channels {g0}..{g0 + len(part) - 1}")
+    return out
+
+
+def dataset(cases: Sequence[Case], traj: np.ndarray, with_length: bool = False, t_min: float = 100.0):
+    """(X, T, w, keep): features, targets (z/H, p/H), weights H^2, and the mask of kept samples
+    (t >= t_min, finite z and p, no instability so far)."""
+    Xs, Ts, ws, keep = [], [], [], []
+    for case, tr in zip(cases, traj):
+        H = float(case.geom.ny - 2)
+        t, z, p, unst = tr[:, 0], tr[:, 1], tr[:, 2], tr[:, 4]
+        ok = (t >= t_min) & np.isfinite(z) & np.isfinite(p) & (unst == 0)
+        Xs.append(features(case, np.maximum(t, 1.0), with_length))
+        Ts.append(np.stack([z / H, p / H], axis=1))
+        ws.append(np.full(t.shape, H * H))
+        keep.append(ok)
+    X = np.concatenate(Xs).astype(np.float32)
+    T = np.concatenate(Ts).astype(np.float32)
+    w = np.concatenate(ws).astype(np.float32)
+    k = np.concatenate(keep)
+    return X, T, w, k
+
+
+def curve_errors(net: Network, cases: Sequence[Case], traj: np.ndarray, with_length: bool = False):
+    """Per-channel max |z_surrogate - z_LBM| and max |p_surrogate - p_LBM| in lattice units over the
+    kept samples, and the fraction of samples inside the training hull."""
+    X, T, w, k = dataset(cases, traj, with_length)
+    Y, inside = net.predict(X)
+    ns = traj.shape[1]
+    errs = []
+    for c, case in enumerate(cases):
+        H = float(case.geom.ny - 2)
+        sl = slice(c * ns, (c + 1) * ns)
+        m = k[sl]
+        if not m.any():
+            errs.append((np.nan, np.nan))
+            continue
+        dz = np.abs(Y[sl][m, 0] - T[sl][m, 0]) * H
+        dp = np.abs(Y[sl][m, 1] - T[sl][m, 1]) * H
+        errs.append((float(dz.max()), float(dp.max())))
+    return np.array(errs), float(inside[k].mean()) if k.any() else 0.0
+
+
+def predict_curves(net: Network, cases: Sequence[Case], t: np.ndarray, with_length: bool = False,
+                   every: int = 100):
+    """z(t), p(t) for each channel at times t: the network inside the training hull, the batched
+    LBM for channels with any query outside it (the fallback).  Returns (Z, P, used_lbm)."""
+    t = np.asarray(t, dtype=np.float64)
+    Z = np.empty((len(cases), t.size)); P = np.empty_like(Z)
+    outside = []
+    for c, case in enumerate(cases):
+        Y, inside = net.predict(features(case, t, with_length))
+        H = float(case.geom.ny - 2)
+        Z[c], P[c] = Y[:, 0] * H, Y[:, 1] * H
+        if not inside.all():
+            outside.append(c)
+    if outside:
+        steps = int(math.ceil(t.max() / every) * every)
+        traj = simulate([cases[c] for c in outside], steps, every)
+        for j, c in enumerate(outside):
+            idx = np.clip(np.rint(t / every).astype(int), 0, traj.shape[1] - 1)
+            Z[c], P[c] = traj[j, idx, 1], traj[j, idx, 2]
+    used = np.zeros(len(cases), bool); used[outside] = True
+    return Z, P, used
+
+
+# ---------------------------------------------------------------------------------------------
+# Command line: generate trajectories, train, evaluate.
+#   python -m paper_0807_0602_amd.surrogate generate --n 1000 --seed 1 --out train1.npz
+#   python -m paper_0807_0602_amd.surrogate train --data train1.npz train2.npz --inputs 5 --out w.npz
+#   python -m paper_0807_0602_amd.surrogate evaluate --weights w.npz --data heldout.npz
+# ---------------------------------------------------------------------------------------------
+
+def save_trajectories(path: str, cases: Sequence[Case], traj: np.ndarray, steps: int, every: int) -> None:
+    from .inputs import TAU_FOR_RATIO
+    ratio_of = {tau: r for r, tau in TAU_FOR_RATIO.items()}
+    meta = np.array([(c.geom.ny - 2, c.geom.x1 - c.geom.x0, c.params.gw[0], ratio_of[tuple(c.params.tau)], c.seed)
+                     for c in cases], dtype=np.float64)
+    np.savez_compressed(path, meta=meta, traj=traj.astype(np.float32), steps=steps, every=every)
+
+
+def load_trajectories(path: str):
+    from .inputs import sweep_channel
+    z = np.load(path)
+    steps, every = int(z["steps"]), int(z["every"])
+    cases = [sweep_channel(int(H), int(L_), float(g), int(r), seed=int(sd), steps=steps, sample_every=every)
+             for H, L_, g, r, sd in z["meta"]]
+    return cases, z["traj"].astype(np.float64)
+
+
+def _main(argv=None) -> int:
+    import argparse
+    import json
+    import time
+    ap = argparse.ArgumentParser(prog="python -m paper_0807_0602_amd.surrogate")
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    g = sub.add_parser("generate")
+    g.add_argument("--n", type=int, required=True); g.add_argument("--seed", type=int, required=True)
+    g.add_argument("--steps", type=int, default=50_000); g.add_argument("--every", type=int, default=100)
+    g.add_argument("--group", type=int, default=64); g.add_argument("--out", required=True)
+    t = sub.add_parser("train")
+    t.add_argument("--data", nargs="+", required=True); t.add_argument("--inputs", type=int, choices=[4, 5], default=5)
+    t.add_argument("--steps", type=int, default=20_000); t.add_argument("--batch", type=int, default=4096)
+    t.add_argument("--lr", type=float, default=1e-3); t.add_argument("--seed", type=int, default=0)
+    t.add_argument("--heldout", default=None); t.add_argument("--out", required=True)
+    e = sub.add_parser("evaluate")
+    e.add_argument("--weights", required=True); e.add_argument("--data", required=True)
+    a = ap.parse_args(argv)
+    say = lambda m: print(m, flush=True)
+    if a.cmd == "generate":
+        cases = draw_cases(a.n, a.seed, a.steps, a.every)
+        t0 = time.perf_counter()
+        traj = simulate(cases, a.steps, a.every, a.group, log=say)
+        dt = time.perf_counter() - t0
+        save_trajectories(a.out, cases, traj, a.steps, a.every)
+        unstable = int((traj[:, -1, 4] > 0).sum())
+        say(json.dumps({"generated": a.n, "seconds": round(dt, 1), "unstable": unstable, "out": a.out}))
+        return 0
+    if a.cmd == "train":
+        cases, trajs = [], []
+        for p in a.data:
+            c, tr = load_trajectories(p); cases += c; trajs.append(tr)
+        traj = np.concatenate(trajs)
+        wl = a.inputs == 5
+        X, T, w, k = dataset(cases, traj, wl)
+        X, T, w = X[k], T[k], w[k]
+        net = Network(a.inputs, 256, 4, max_batch=a.batch, max_data=X.shape[0], lr=a.lr, seed=a.seed)
+        net.set_data(X, T, w)
+        t0 = time.perf_counter()
+        losses = []
+        chunk = 1000
+        for s0 in range(0, a.steps, chunk):
+            losses.append(net.train(min(chunk, a.steps - s0), a.batch))
+            say(f"step {s0 + chunk}: minibatch loss {losses[-1]:.4f} (lattice units^2)")
+        dt = time.perf_counter() - t0
+        info = {"train_rows": int(X.shape[0]), "train_channels": len(cases), "steps": a.steps, "batch": a.batch,
+                "seconds": round(dt, 1), "final_loss": losses[-1]}
+        if a.heldout:
+            hc, ht = load_trajectories(a.heldout)
+            errs, inside = curve_errors(net, hc, ht, wl)
+            ok = np.isfinite(errs[:, 0])
+            info.update({"heldout_channels": int(ok.sum()), "heldout_max_dz": float(np.nanmax(errs[:, 0])),
+                         "heldout_median_max_dz": float(np.nanmedian(errs[:, 0])),
+                         "heldout_frac_le_1lu": float(np.mean(errs[ok, 0] <= 1.0)), "inside_hull": inside})
+        net.save(a.out, info=json.dumps(info))
+        say(json.dumps(info))
+        return 0
+    if a.cmd == "evaluate":
+        z = np.load(a.weights)
+        net = Network.load(a.weights)
+        hc, ht = load_trajectories(a.data)
+        errs, inside = curve_errors(net, hc, ht, int(z["d_in"]) == 5)
+        ok = np.isfinite(errs[:, 0])
+        say(json.dumps({"channels": int(ok.sum()), "max_dz": float(np.nanmax(errs[:, 0])),
+                        "median_max_dz": float(np.nanmedian(errs[:, 0])),
+                        "frac_le_1lu": float(np.mean(errs[ok, 0] <= 1.0)), "inside_hull": inside}))
+        return 0
+    return 2
+
+
+if __name__ == "__main__":
+    raise SystemExit(_main())
