@@ -13,6 +13,11 @@ Prints ONE JSON line.  Options: --steps K (timed), --warmup W, --gpus N (only 1 
 --variant fused|two_kernel, --no-cpu-baseline, --calibrate-copy (runs only a plain copy kernel,
 for counter calibration under rocprofv3), --tile BX CY ORDER (skip the autotuner).
 
+--workload surrogate measures the learned surrogate against the batched LBM on 64 fresh
+channels drawn like its training set (seed 3): the LBM simulates them (points/hour of the LBM)
+and judges the network's curves (max |z_surrogate - z_LBM| per channel, lattice units); the
+network's points/hour come from timed inference of the same curves.
+
 --workload sweep measures the batched calibration sweep instead: 64 channels with H in
 {20, 40, 80, 160}, L in {512, ..., 4096}, G_wA uniform in [-0.3, 0.3] (G_wB = -G_wA) and a
 viscosity-ratio tau pair, advanced together (one launch per step over all their tiles, HIP
@@ -185,6 +190,51 @@ def sweep(args) -> int:
     return 0
 
 
+def surrogate_gain(args) -> int:
+    import numpy as np
+    import torch
+    from paper_0807_0602_amd import surrogate as S
+
+    steps = args.steps if args.steps != 10000 else 50_000
+    every = 100
+    net = S.Network.load(args.weights)
+    wl = net.cfg.d_in == 5
+    cases = S.draw_cases(64, seed=3, steps=steps, every=every)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    traj = S.simulate(cases, steps, every)
+    torch.cuda.synchronize()
+    lbm_s = time.perf_counter() - t0
+    errs, inside = S.curve_errors(net, cases, traj, wl)
+    X, T, w, k = S.dataset(cases, traj, wl)
+    net.predict(X)                       # warm-up
+    reps = 20
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        net.predict(X)
+    sur_s = (time.perf_counter() - t0) / reps
+    ok = np.isfinite(errs[:, 0])
+    within = float(np.mean(errs[ok, 0] <= 1.0))
+    lbm_pph = len(cases) * 3600.0 / lbm_s
+    sur_pph = len(cases) * 3600.0 / sur_s
+    line = {
+        "metric": "calibration-sweep points/hour: learned surrogate vs batched LBM (one point = one channel's z(t), p(t))",
+        "value": round(sur_pph, 1), "unit": "points/h", "n_gpus": 1, "steps": steps, "warmup": 1,
+        "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "bf16 MFMA / f32 accumulate (network), f32 (LBM)", "data": "synthetic",
+        "config": {"workload": "surrogate_vs_lbm_64_channels", "inputs": int(net.cfg.d_in),
+                   "lbm_points_per_hour": round(lbm_pph, 1), "surrogate_points_per_hour": round(sur_pph, 1),
+                   "speedup": round(sur_pph / lbm_pph, 1), "judged_channels": int(ok.sum()),
+                   "max_dz_lu": float(np.nanmax(errs[:, 0])), "median_max_dz_lu": float(np.nanmedian(errs[:, 0])),
+                   "fraction_within_1lu": round(within, 4),
+                   "points_per_hour_within_1lu": round(sur_pph * within, 1),
+                   "inside_training_hull": round(inside, 4), "samples_per_point": int(traj.shape[1])},
+    }
+    print(json.dumps(line), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -194,7 +244,8 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true")
     ap.add_argument("--tile", type=int, nargs=3, default=None, metavar=("BX", "CY", "ORDER"))
-    ap.add_argument("--workload", choices=["roofline", "sweep"], default="roofline")
+    ap.add_argument("--workload", choices=["roofline", "sweep", "surrogate"], default="roofline")
+    ap.add_argument("--weights", default=os.path.join(ROOT, "paper_0807_0602_amd", "surrogate_weights_5in.npz"))
     ap.add_argument("--summarize-counters", nargs=4, default=None,
                     metavar=("FETCH_CSV", "WRITE_CSV", "FETCH_COPY_CSV", "WRITE_COPY_CSV"),
                     help="write the traffic summary for the schedule given by --tile and exit")
@@ -215,6 +266,8 @@ def main() -> int:
         return 0
     if args.workload == "sweep":
         return sweep(args)
+    if args.workload == "surrogate":
+        return surrogate_gain(args)
 
     from paper_0807_0602_amd import _lib as L
     from paper_0807_0602_amd import inputs
