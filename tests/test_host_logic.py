@@ -1,0 +1,88 @@
+"""Host-side logic without a GPU: surrogate features and dataset masking, trajectory files, the
+counter summary of bench.py."""
+import csv
+import json
+import math
+import os
+import sys
+
+import numpy as np
+
+from paper_0807_0602_amd import inputs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_features_and_dataset_masking(tmp_path):
+    from paper_0807_0602_amd import surrogate as S
+    cases = S.draw_cases(3, seed=4, steps=500, every=100)
+    for c in cases:
+        H = c.geom.ny - 2
+        L = c.geom.x1 - c.geom.x0
+        assert 20 <= H <= 160 and 512 <= L <= 4096 and L % 4 == 0 and -0.3 <= c.params.gw[0] <= 0.3
+        assert tuple(c.params.tau) in inputs.TAU_FOR_RATIO.values()
+    f = S.features(cases[0], np.array([100.0, 1000.0]), with_length=True)
+    c0 = cases[0]
+    np.testing.assert_allclose(f[:, 0], c0.params.gw[0], rtol=1e-6)
+    np.testing.assert_allclose(f[:, 1], math.log(c0.params.tau[1] / c0.params.tau[0]), rtol=1e-6)
+    np.testing.assert_allclose(f[:, 2], c0.geom.ny - 2)
+    np.testing.assert_allclose(f[:, 3], np.log([100.0, 1000.0]), rtol=1e-6)
+    np.testing.assert_allclose(f[:, 4], math.log(c0.geom.x1 - c0.geom.x0), rtol=1e-6)
+    # trajectories: t, z, p, flags, unstable-so-far
+    ns = 6
+    traj = np.zeros((3, ns, 5))
+    traj[:, :, 0] = np.arange(ns) * 100
+    traj[:, :, 1] = 2.0
+    traj[:, :, 2] = 3.0
+    traj[1, 3, 1] = np.nan            # missing front: dropped
+    traj[2, 4:, 4] = 1.0              # unstable from sample 4 on: dropped
+    X, T, w, k = S.dataset(cases, traj)
+    assert X.shape == (3 * ns, 4) and T.shape == (3 * ns, 2)
+    keep = k.reshape(3, ns)
+    assert not keep[:, 0].any()       # t = 0 < t_min
+    assert keep[0, 1:].all() and not keep[1, 3] and keep[1, 4] and not keep[2, 4:].any()
+    H = np.repeat([c.geom.ny - 2 for c in cases], ns)
+    np.testing.assert_allclose(w, H * H)
+    np.testing.assert_allclose(T[k, 0], (2.0 / H)[k], rtol=1e-6)
+    # file round trip
+    p = str(tmp_path / "t.npz")
+    S.save_trajectories(p, cases, traj, 500, 100)
+    c2, t2 = S.load_trajectories(p)
+    for a, b in zip(cases, c2):
+        assert a.geom == b.geom and a.params == b.params and a.seed == b.seed
+    assert np.array_equal(np.isnan(t2), np.isnan(traj))
+    np.testing.assert_allclose(np.nan_to_num(t2), np.nan_to_num(traj), rtol=1e-6)
+
+
+def _counter_csv(path, kernel, counter, values):
+    with open(path, "w", newline="") as f:
+        w = csv.DictWriter(f, fieldnames=["Kernel_Name", "Counter_Name", "Counter_Value"])
+        w.writeheader()
+        for v in values:
+            w.writerow({"Kernel_Name": kernel, "Counter_Name": counter, "Counter_Value": v})
+
+
+def test_bench_counter_summary(tmp_path, monkeypatch):
+    sys.path.insert(0, ROOT)
+    import bench
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(tmp_path / "traffic.json"))
+    files = []
+    for name, kern, ctr, vals in [("f", "k_step_fused<256>", "FETCH_SIZE", [600000, 600000]),
+                                  ("w", "k_step_fused<256>", "WRITE_SIZE", [1179000]),
+                                  ("fc", "__amd_rocclr_copyBuffer", "FETCH_SIZE", [524288]),
+                                  ("wc", "__amd_rocclr_copyBuffer", "WRITE_SIZE", [1048576])]:
+        p = str(tmp_path / f"{name}.csv")
+        _counter_csv(p, kern, ctr, vals)
+        files.append(p)
+
+    class A:
+        summarize_counters = files
+        tile = [256, 16, 1]
+    assert bench.summarize_counters(A) == 0
+    t = json.load(open(tmp_path / "traffic.json"))
+    e = t["schedules"][0]
+    assert e["fetch_scale"] == 2.0 and e["write_scale"] == 1.0
+    assert e["read_bytes_per_launch"] == 600000 * 2 * 1024 and e["write_bytes_per_launch"] == 1179000 * 1024
+    cells = 16384 * 1024
+    assert bench.measured_traffic(cells, {"bx": 256, "cy": 16, "order": 1}) == e["bytes_per_launch"]
+    assert bench.measured_traffic(cells, {"bx": 256, "cy": 8, "order": 1}) is None
