@@ -81,7 +81,7 @@ typedef struct {
 
 /* Launch schedule of the fused step (see scf_set_tile). */
 typedef struct {
-    int32_t bx;           /* block width in nodes along x: 64, 128 or 256 */
+    int32_t bx;           /* block width in nodes along x: 64, 128, 256 or 512 */
     int32_t cy;           /* rows per tile, >= 1 (>= ny: whole columns) */
     int32_t order;        /* tile order: SCF_ORDER_STRIPS (all row chunks of a strip, then the next
                              strip) or SCF_ORDER_BANDS (all strips of a row band, then the next
@@ -234,6 +234,7 @@ int64_t scf_sur_param_count(const scf_sur* s);
 int scf_sur_get_params(scf_sur* s, float* out);        /* host copy, param_count floats */
 int scf_sur_set_params(scf_sur* s, const float* in);   /* also refreshes the BF16 copies */
 int scf_sur_reset_optimizer(scf_sur* s);               /* Adam moments and step count to 0 */
+int scf_sur_set_lr(scf_sur* s, float lr);              /* Adam step size for later updates, > 0 */
 
 /* Copy n training rows (host: X n*d_in, T n*2, optional per-row weights w, NULL = 1) to the
  * device and compute there the per-input mean, standard deviation, min and max (the training

@@ -103,6 +103,7 @@ _sig = {
     "scf_sur_get_params": (C.c_int, [_vp, _fp]),
     "scf_sur_set_params": (C.c_int, [_vp, _fp]),
     "scf_sur_reset_optimizer": (C.c_int, [_vp]),
+    "scf_sur_set_lr": (C.c_int, [_vp, C.c_float]),
     "scf_sur_set_data": (C.c_int, [_vp, _fp, _fp, _fp, C.c_int64]),
     "scf_sur_get_norm": (C.c_int, [_vp, _fp, _fp, _fp, _fp]),
     "scf_sur_set_norm": (C.c_int, [_vp, _fp, _fp, _fp, _fp]),

@@ -593,6 +593,7 @@ hipError_t launch_step_fused(int bx, const Chan* chans, const TileDesc* tiles, i
         case 64: return launch_fused_bx<64>(chans, tiles, ntiles, grid, ws, src, s);
         case 128: return launch_fused_bx<128>(chans, tiles, ntiles, grid, ws, src, s);
         case 256: return launch_fused_bx<256>(chans, tiles, ntiles, grid, ws, src, s);
+        case 512: return launch_fused_bx<512>(chans, tiles, ntiles, grid, ws, src, s);
         default: return hipErrorInvalidValue;
     }
 }

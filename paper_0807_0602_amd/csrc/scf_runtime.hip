@@ -375,7 +375,8 @@ struct Engine {
 
     int set_tile(const scf_tile* tl) {
         if (!tl) return fail(SCF_EINVAL, "tile is NULL");
-        if (tl->bx != 64 && tl->bx != 128 && tl->bx != 256) return fail(SCF_EINVAL, "bx must be 64, 128 or 256");
+        if (tl->bx != 64 && tl->bx != 128 && tl->bx != 256 && tl->bx != 512)
+            return fail(SCF_EINVAL, "bx must be 64, 128, 256 or 512");
         if (tl->cy < 1) return fail(SCF_EINVAL, "cy must be >= 1");
         if (tl->order < 0 || tl->order > (SCF_ORDER_BANDS | SCF_ORDER_XCD)) return fail(SCF_EINVAL, "unknown order");
         if (tl->graph_steps < 0) return fail(SCF_EINVAL, "graph_steps must be >= 0");
@@ -399,7 +400,7 @@ struct Engine {
         HIP_TRY(hipStreamSynchronize(stream));
         int maxny = 0;
         for (auto& g : geom) maxny = std::max(maxny, g.ny);
-        const int bxs[3] = {64, 128, 256};
+        const int bxs[4] = {64, 128, 256, 512};
         const int cys[8] = {4, 8, 16, 32, 48, 64, 128, 1 << 30};
         hipEvent_t e0, e1;
         HIP_TRY(hipEventCreate(&e0));

@@ -29,7 +29,7 @@ hipError_t output_grad(const float* Z, int width, int rows, const float* dY, flo
                        hipStream_t s);
 hipError_t loss_sum(const float* rowloss, int rows, float inv_n, float* out, hipStream_t s);
 hipError_t adam(float* theta, const float* grad, float* m1, float* m2, int64_t n, int64_t* step,
-                float lr, float b1, float b2, float eps, hipStream_t s);
+                const float* lr, float b1, float b2, float eps, hipStream_t s);
 hipError_t shadow(const float* W, int n_out, int n_in, __bf16* Wb, __bf16* WbT, hipStream_t s);
 hipError_t stats(const float* X, int d_in, int64_t n, float* mean, float* stdv, float* lo, float* hi,
                  hipStream_t s);

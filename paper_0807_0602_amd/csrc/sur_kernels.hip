@@ -267,16 +267,17 @@ k_loss_sum(const float* __restrict__ rowloss, int rows, float inv_n, float* __re
 }
 
 // ---------------------------------------------------------------------------------------------
-// Adam (Kingma and Ba, 2015) with bias correction; the step count lives on the device so that
-// captured graphs advance it.  Hidden weight matrices are copied to BF16, row-major and
+// Adam (Kingma and Ba, 2015) with bias correction; the step count and the learning rate live on
+// the device so that captured graphs advance the one and follow changes of the other.  Hidden weight matrices are copied to BF16, row-major and
 // transposed.
 // ---------------------------------------------------------------------------------------------
 __global__ void __launch_bounds__(kThreads)
 k_adam(float* __restrict__ theta, const float* __restrict__ grad, float* __restrict__ m1,
-       float* __restrict__ m2, int64_t n, const int64_t* __restrict__ step, float lr, float b1,
-       float b2, float eps) {
+       float* __restrict__ m2, int64_t n, const int64_t* __restrict__ step,
+       const float* __restrict__ lr_dev, float b1, float b2, float eps) {
     const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
     if (i >= n) return;
+    const float lr = *lr_dev;
     const float t = (float)(*step + 1);
     const float g = grad[i];
     const float a = b1 * m1[i] + (1.0f - b1) * g;
@@ -469,7 +470,7 @@ hipError_t loss_sum(const float* rowloss, int rows, float inv_n, float* out, hip
 }
 
 hipError_t adam(float* theta, const float* grad, float* m1, float* m2, int64_t n, int64_t* step,
-                float lr, float b1, float b2, float eps, hipStream_t s) {
+                const float* lr, float b1, float b2, float eps, hipStream_t s) {
     hipLaunchKernelGGL(k_adam, grid1(n), dim3(kThreads), 0, s, theta, grad, m1, m2, n, step, lr, b1, b2,
                        eps);
     hipError_t e = hipGetLastError();

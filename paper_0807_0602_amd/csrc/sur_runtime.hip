@@ -33,7 +33,7 @@ size_t al(size_t v) { return (v + 255) / 256 * 256; }
 struct Plan {
     size_t total = 0;
     size_t theta, grad, m1, m2, wb, wbt, mean, stdv, lo, hi, Xd, Td, wd, Xs, Ts, wsb, Xn, Tb, wbb,
-        Z, H, HT, dZ, dZb, dZbT, Y, dY, rowloss, loss, step, inhull;
+        Z, H, HT, dZ, dZb, dZbT, Y, dY, rowloss, loss, step, inhull, lr;
     int64_t P = 0;
     std::vector<int64_t> woff, boff;   // per layer, in floats
 };
@@ -99,6 +99,7 @@ Plan plan(const scf_sur_cfg& c) {
     p.loss = take(4);
     p.step = take(8);
     p.inhull = take((size_t)B);
+    p.lr = take(4);
     p.total = o;
     return p;
 }
@@ -175,8 +176,8 @@ struct scf_sur {
     }
 
     hipError_t adam_and_shadows(hipStream_t s) const {
-        hipError_t e = scf::sur::adam(theta(), grad(), at<float>(p.m1), at<float>(p.m2), p.P, step(), cfg.lr,
-                                      cfg.beta1, cfg.beta2, cfg.eps, s);
+        hipError_t e = scf::sur::adam(theta(), grad(), at<float>(p.m1), at<float>(p.m2), p.P, step(),
+                                      at<float>(p.lr), cfg.beta1, cfg.beta2, cfg.eps, s);
         return e == hipSuccess ? shadows(s) : e;
     }
 
@@ -235,6 +236,10 @@ int scf_sur_create(scf_sur** out, const scf_sur_cfg* cfg, void* dev_ws, size_t w
     std::vector<float> ones(cfg->d_in, 1.0f);
     e = hipMemcpyAsync(s->at<float>(p.stdv), ones.data(), sizeof(float) * cfg->d_in, hipMemcpyHostToDevice, st);
     if (e != hipSuccess) return fail("hipMemcpyAsync", e);
+    e = hipMemcpyAsync(s->at<float>(p.lr), &cfg->lr, sizeof(float), hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return fail("hipMemcpyAsync", e);
+    e = hipStreamSynchronize(st);   // the host sources above go out of scope
+    if (e != hipSuccess) return fail("hipStreamSynchronize", e);
     for (int l = 0; l <= cfg->depth && e == hipSuccess; ++l) {
         const int o = l == cfg->depth ? 2 : cfg->width, i = l == 0 ? cfg->d_in : cfg->width;
         e = scf::sur::init_params(s->theta(), p.woff[l], o, i, cfg->seed * 1000003ull + (uint64_t)l, st);
@@ -259,6 +264,14 @@ int scf_sur_set_params(scf_sur* s, const float* in) {
     if (!s || !in) return set_error(SCF_EINVAL, "NULL argument");
     SUR_TRY(hipMemcpyAsync(s->theta(), in, sizeof(float) * s->p.P, hipMemcpyHostToDevice, s->stream));
     SUR_TRY(s->shadows(s->stream));
+    SUR_TRY(hipStreamSynchronize(s->stream));
+    return SCF_OK;
+}
+
+int scf_sur_set_lr(scf_sur* s, float lr) {
+    if (!s) return set_error(SCF_EINVAL, "NULL argument");
+    if (!(lr > 0.0f)) return set_error(SCF_EINVAL, "lr must be > 0");
+    SUR_TRY(hipMemcpyAsync(s->at<float>(s->p.lr), &lr, sizeof(float), hipMemcpyHostToDevice, s->stream));
     SUR_TRY(hipStreamSynchronize(s->stream));
     return SCF_OK;
 }

@@ -75,6 +75,9 @@ class Network:
     def reset_optimizer(self) -> None:
         L.check(L.scf_sur_reset_optimizer(self._h))
 
+    def set_lr(self, lr: float) -> None:
+        L.check(L.scf_sur_set_lr(self._h, float(lr)))
+
     def set_data(self, X: np.ndarray, T: np.ndarray, w: Optional[np.ndarray] = None) -> None:
         X = np.ascontiguousarray(X, np.float32); T = np.ascontiguousarray(T, np.float32)
         wp = None
@@ -311,6 +314,9 @@ def _main(argv=None) -> int:
         losses = []
         chunk = 1000
         for s0 in range(0, a.steps, chunk):
+            # cosine decay of the step size down to 1 % over the run
+            frac = s0 / max(1, a.steps)
+            net.set_lr(a.lr * (0.01 + 0.99 * 0.5 * (1.0 + math.cos(math.pi * frac))))
             losses.append(net.train(min(chunk, a.steps - s0), a.batch))
             say(f"step {s0 + chunk}: minibatch loss {losses[-1]:.4f} (lattice units^2)")
         dt = time.perf_counter() - t0
