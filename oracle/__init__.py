@@ -59,6 +59,7 @@ def lib():
         L.orc_create.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_double,
                                  dp, dp, dp, dp]
         L.orc_destroy.argtypes = [C.c_void_p]
+        L.orc_set_mask.argtypes = [C.c_void_p, C.c_void_p]
         L.orc_set_threads.argtypes = [C.c_int]
         L.orc_threads.restype = C.c_int
         L.orc_init.argtypes = [C.c_void_p, dp, dp]
@@ -101,21 +102,28 @@ class Oracle:
 
     def __init__(self, nx: int, ny: int, x0: int = 0, x1: int = 0, G: float = 0.9,
                  gw=(0.0, 0.0), tau=(1.0, 1.0), alpha=(4.0 / 9.0, 4.0 / 9.0), mass=(1.0, 1.0),
-                 periodic_x: bool = True):
+                 periodic_x: bool = True, solid: Optional[np.ndarray] = None):
         self.nx, self.ny, self.x0, self.x1 = int(nx), int(ny), int(x0), int(x1)
         self._keep = [_d2(gw), _d2(tau), _d2(alpha), _d2(mass)]
         self._h = lib().orc_create(self.nx, self.ny, self.x0, self.x1, int(bool(periodic_x)),
                                    float(G), *[_dp(a) for a in self._keep])
         if not self._h:
             raise ValueError("oracle: bad geometry")
+        if solid is not None:
+            m = np.ascontiguousarray(np.asarray(solid) != 0, dtype=np.uint8)
+            assert m.shape == (self.ny, self.nx)
+            lib().orc_set_mask(self._h, m.ctypes.data)
 
     @classmethod
     def from_case(cls, case, periodic_x: bool = True, x_offset: int = 0, width: Optional[int] = None):
         """Oracle for a Case; with x_offset/width, a window of columns (x clamped at its edges)."""
         g, p = case.geom, case.params
         nx = g.nx if width is None else width
+        solid = getattr(g, "solid", None)
+        if solid is not None:
+            solid = np.asarray(solid)[:, x_offset:x_offset + nx]
         return cls(nx, g.ny, g.x0 - x_offset, g.x1 - x_offset, p.G, p.gw, p.tau, p.alpha, p.mass,
-                   periodic_x=periodic_x)
+                   periodic_x=periodic_x, solid=solid)
 
     def __del__(self):
         h = getattr(self, "_h", None)

@@ -45,6 +45,7 @@ struct orc {
     double* f;     /* [2][9][ny][nx] state f(x, t) */
     double* fs;    /* [2][9][ny][nx] post-collision f*(x, t) */
     double* n;     /* [2][ny][nx] densities of the current state (scratch) */
+    unsigned char* mask;   /* optional [ny][nx] solid mask (non-zero = solid), replaces the rows */
 };
 
 static int g_threads = 1;
@@ -56,6 +57,7 @@ int orc_threads(void) { return g_threads; }
 #define NIDX(s, k, y, x) (((size_t)(k) * (s)->ny + (y)) * (size_t)(s)->nx + (x))
 
 static int is_solid(const orc_t* s, int x, int y) {
+    if (s->mask) return s->mask[(size_t)y * s->nx + x] != 0;
     return (y == 0 || y == s->ny - 1) && x >= s->x0 && x < s->x1;
 }
 
@@ -85,7 +87,15 @@ orc_t* orc_create(int nx, int ny, int x0, int x1, int periodic_x, double G, cons
 
 void orc_destroy(orc_t* s) {
     if (!s) return;
-    free(s->f); free(s->fs); free(s->n); free(s);
+    free(s->f); free(s->fs); free(s->n); free(s->mask); free(s);
+}
+
+void orc_set_mask(orc_t* s, const unsigned char* mask) {
+    free(s->mask);
+    s->mask = NULL;
+    if (!mask) return;
+    s->mask = (unsigned char*)malloc((size_t)s->ny * s->nx);
+    memcpy(s->mask, mask, (size_t)s->ny * s->nx);
 }
 
 int64_t orc_time(const orc_t* s) { return s->t; }

@@ -37,6 +37,10 @@ orc_t* orc_create(int nx, int ny, int x0, int x1, int periodic_x,
                   double G, const double gw[2], const double tau[2],
                   const double alpha[2], const double mass[2]);
 void orc_destroy(orc_t*);
+/* Optional solid mask, ny*nx row-major, non-zero = solid; it replaces the wall rows of
+ * orc_create (x0, x1 then only place the observables).  Copied.  NULL restores the rows.
+ * Call before orc_init. */
+void orc_set_mask(orc_t*, const unsigned char* mask);
 void orc_set_threads(int nthreads);
 int  orc_threads(void);
 

@@ -57,13 +57,22 @@ def uniform_pm1(seed: int, comp: int, ys: np.ndarray, xs: np.ndarray) -> np.ndar
 
 @dataclass(frozen=True)
 class Geometry:
-    """Box nx by ny, periodic in x and y, solid rows y=0 and y=ny-1 over x in [x0, x1)."""
+    """Box nx by ny, periodic in x and y, solid rows y=0 and y=ny-1 over x in [x0, x1).
+
+    ``solid`` (optional, (ny, nx), non-zero = solid) replaces the rows as the set of solid
+    nodes; x0 and x1 then only place the observables (inlet x0, reservoir centre x0/2).
+    """
     nx: int
     ny: int
     x0: int = 0
     x1: int = 0
+    solid: Optional[np.ndarray] = field(default=None, compare=False, repr=False)
 
     def solid_mask(self) -> np.ndarray:
+        if self.solid is not None:
+            m = np.asarray(self.solid) != 0
+            assert m.shape == (self.ny, self.nx)
+            return m.copy()
         m = np.zeros((self.ny, self.nx), dtype=bool)
         if self.x1 > self.x0:
             m[0, self.x0:self.x1] = True
@@ -121,9 +130,7 @@ class Case:
         if self.noise:
             rhoA = rhoA + self.noise * uniform_pm1(self.seed, 0, Y, X)
             rhoB = rhoB + self.noise * uniform_pm1(self.seed, 1, Y, X)
-        solid = np.zeros_like(liquid)
-        if g.x1 > g.x0:
-            solid = ((Y == 0) | (Y == g.ny - 1)) & (X >= g.x0) & (X < g.x1)
+        solid = g.solid_mask()[:, xs_glob]
         rhoA[solid] = 0.0
         rhoB[solid] = 0.0
         return np.ascontiguousarray(rhoA), np.ascontiguousarray(rhoB)
@@ -138,6 +145,38 @@ def capillary_small(seed: int = 1) -> Case:
     """200 x 24 box, channel x in [50,150), H = 22, G_w = (-0.2, +0.2), tau = (1, 1)."""
     return Case(Geometry(200, 24, 50, 150), Params(G=0.9, gw=(-0.2, 0.2), tau=(1.0, 1.0)),
                 seed=seed, steps=2000, sample_every=10, name="capillary_200x24")
+
+
+def rough_mask(nx: int, ny: int, x0: int, x1: int, seed: int, bumps: int = 12,
+               post: Optional[Tuple[int, int, int, int]] = None) -> np.ndarray:
+    """Solid mask of a capillary with rough walls: the wall rows over [x0, x1) plus `bumps`
+    one- or two-node-high steps on each wall at seeded positions, and an optional solid post
+    (xa, xb, ya, yb) inside the channel.  Geometry only; no model arithmetic."""
+    m = np.zeros((ny, nx), dtype=np.uint8)
+    m[0, x0:x1] = 1
+    m[ny - 1, x0:x1] = 1
+    rng = np.random.default_rng(seed)
+    for wall in (0, 1):
+        xs = rng.integers(x0, max(x0 + 1, x1 - 3), size=bumps)
+        ws = rng.integers(1, 4, size=bumps)
+        hs = rng.integers(1, 3, size=bumps)
+        for x, w, h in zip(xs, ws, hs):
+            rows = range(1, 1 + h) if wall == 0 else range(ny - 1 - h, ny - 1)
+            for y in rows:
+                m[y, x:min(x + w, x1)] = 1
+    if post is not None:
+        xa, xb, ya, yb = post
+        m[ya:yb, xa:xb] = 1
+    return m
+
+
+def capillary_rough(seed: int = 1, post: bool = True) -> Case:
+    """The 200 x 24 capillary with rough walls (seeded steps on both walls) and, optionally, a
+    4 x 4 solid post at x = 96..100, y = 6..9, below the centre line (general solid mask)."""
+    nx, ny, x0, x1 = 200, 24, 50, 150
+    m = rough_mask(nx, ny, x0, x1, seed=100 + seed, post=(96, 100, 6, 10) if post else None)
+    return Case(Geometry(nx, ny, x0, x1, solid=m), Params(G=0.9, gw=(-0.2, 0.2), tau=(1.0, 1.0)),
+                seed=seed, steps=2000, sample_every=10, name="capillary_rough_200x24")
 
 
 # Relaxation-time pairs (tau_A, tau_B) realising a dynamic-viscosity ratio r = nu_A/nu_B between

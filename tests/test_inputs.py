@@ -55,3 +55,18 @@ def test_sweep_draws_cover_the_sets():
     for c in d:
         assert -0.3 <= c.params.gw[0] <= 0.3 and c.params.gw[1] == -c.params.gw[0]
         assert c.geom.nx == 3 * (c.geom.x1 - c.geom.x0) // 2
+
+
+def test_rough_mask_geometry():
+    case = inputs.capillary_rough(seed=1)
+    g = case.geom
+    m = g.solid_mask()
+    rows = inputs.Geometry(g.nx, g.ny, g.x0, g.x1).solid_mask()
+    assert np.all(m[rows])                                  # contains the wall rows
+    assert not m[:, :g.x0].any() and not m[:, g.x1:].any()   # reservoirs stay free
+    assert m[6:10, 96:100].all()                             # the post
+    assert not m[g.ny // 2 - 1:g.ny // 2 + 1].any()           # centre line free
+    assert np.array_equal(m, inputs.capillary_rough(seed=1).geom.solid_mask())
+    a, b = case.fields()
+    assert np.all(a[m] == 0) and np.all(b[m] == 0) and np.all(a[~m] > 0)
+    assert g == inputs.Geometry(g.nx, g.ny, g.x0, g.x1)      # the mask is not part of equality

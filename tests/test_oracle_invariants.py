@@ -25,6 +25,18 @@ def test_mass_conservation_capillary():
         assert abs(m1[k] - m0[k]) / m0[k] <= 1e-12
 
 
+def test_mass_conservation_rough_capillary():
+    """Bounce-back conserves mass for any solid shape (rough walls and a post)."""
+    case = inputs.capillary_rough(seed=1)
+    o = oracle.Oracle.from_case(case).init(*case.fields())
+    m0 = o.observe()["mass"]
+    o.step(1000)
+    obs = o.observe()
+    for k in range(2):
+        assert abs(obs["mass"][k] - m0[k]) / m0[k] <= 1e-12
+    assert obs["flags"] == 0
+
+
 def test_momentum_conservation_without_walls():
     rng = np.random.default_rng(11)
     nx, ny = 24, 16
