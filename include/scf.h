@@ -18,7 +18,8 @@
  *  - Geometry: a box nx x ny, periodic in x and y.  Rows y = 0 and y = ny-1 are solid for
  *    x in [x0, x1) (the coated capillary, bounce-back walls); elsewhere those rows are fluid
  *    (the reservoir).  Channel height H = ny - 2.  Liquid (component A) is expected to start
- *    at x < x0; observables are reported relative to x0.
+ *    at x < x0; observables are reported relative to x0.  An optional solid mask
+ *    (scf_geometry.solid) replaces the rows by any set of solid nodes (rough walls, posts).
  *  - Field arrays are row-major (ny rows of nx values, x fastest), FP64 on the host.  The
  *    device state is FP32.
  *  - Threading: one context per stream; distinct contexts are independent.  Calls on one
@@ -54,6 +55,12 @@ enum {
 typedef struct {
     int32_t nx, ny;    /* box size, nx >= 3, ny >= 3, nx < 2^20, ny < 2^20 */
     int32_t x0, x1;    /* solid rows y = 0 and y = ny-1 for x in [x0, x1); x0 == x1: no walls */
+    const uint8_t* solid;  /* optional host mask, ny*nx bytes row-major, non-zero = solid node.
+                              When given it REPLACES the wall rows as the set of solid nodes
+                              (bounce-back, psi = 0, and s = 1 in eq. forcingw all follow it);
+                              x0, x1 then only place the observables (inlet x0, reservoir centre
+                              x0/2).  Read during *_init only (copied); NULL: the wall rows.
+                              A masked channel takes one more FP32 plane of workspace. */
 } scf_geometry;
 
 typedef struct {

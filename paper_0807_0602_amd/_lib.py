@@ -20,7 +20,8 @@ ERROR_NAMES = {SCF_EINVAL: "SCF_EINVAL", SCF_ENOMEM: "SCF_ENOMEM", SCF_EDEVICE: 
 
 
 class scf_geometry(C.Structure):
-    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("x0", C.c_int32), ("x1", C.c_int32)]
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("x0", C.c_int32), ("x1", C.c_int32),
+                ("solid", C.c_void_p)]
 
 
 class scf_params(C.Structure):

@@ -11,12 +11,14 @@ namespace scf {
 // Device region of a channel, in floats from the workspace base:
 //   off + b*18*plane     population buffer b in {0,1}: [k][i][y][pitch], k = A,B; i = 0..8
 //   off + 36*plane       density field [k][y][pitch]
+//   off + 38*plane       (masked channels) solid-neighbourhood codes, uint16 [y][pitch]
 struct Chan {
     int32_t nx, ny, pitch, x0, x1, xs;   // xs = x0/2: liquid-reservoir centre (scan start)
     int32_t row_base;                    // first entry of this channel in the packed row list
-    int32_t pad0;
+    int32_t masked;                      // 1: solid nodes from the mask codes, 0: wall rows
     int64_t off;                         // float offset of population buffer 0
     int64_t plane;                       // ny * pitch
+    int64_t moff;                        // float offset of the code field (masked channels)
     float G;                             // bulk coupling (D2Q9 weights)
     float gw[2];                         // wall couplings
     float omega[2];                      // 1/tau_k
@@ -56,9 +58,10 @@ struct TileDesc {
 };
 
 // Kernel launchers (all asynchronous on `stream`; return hipSuccess or the launch error).
+// launch_init builds the masked channels' codes, then the initial populations.
 hipError_t launch_init(const Chan* chans, const RowRef* rows, int nrows, float* ws, hipStream_t s);
-hipError_t launch_step_fused(int bx, const Chan* chans, const TileDesc* tiles, int ntiles,
-                             int grid, float* ws, int src, hipStream_t s);
+hipError_t launch_step_fused(int bx, bool masked, const Chan* chans, const TileDesc* tiles,
+                             int ntiles, int grid, float* ws, int src, hipStream_t s);
 hipError_t launch_step_two_kernel(const Chan* chans, const RowRef* rows, int nrows, float* ws,
                                   int src, hipStream_t s);
 hipError_t launch_observe(const Chan* chans, const RowRef* rows, int nrows, int nchan, float* ws,

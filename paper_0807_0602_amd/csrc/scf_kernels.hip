@@ -5,7 +5,8 @@
 // (eqs. feq1-feq3) is evaluated at a shifted velocity u_k^eq = U + tau_k F_k / rho_k, with the
 // common velocity U = sum_k (rho_k u_k / tau_k) / sum_k (rho_k / tau_k), the bulk
 // pseudo-potential force of eq. forcing (psi = n, cross-component coupling only) and the wall
-// force of eq. forcingw.  Walls are solid rows with half-way bounce-back (Sec. 3, Fig. 1).
+// force of eq. forcingw.  Walls are solid rows with half-way bounce-back (Sec. 3, Fig. 1), or
+// the nodes of an optional solid mask.
 //
 // Storage: FP32, structure of arrays per component and direction, rows padded to 64 floats.
 // The resident buffer holds POST-COLLISION populations f*(t-1); a step pulls
@@ -17,6 +18,11 @@
 //   cx:  0  1  0 -1  0  1 -1 -1  1
 //   cy:  0  0  1  0 -1  1  1 -1 -1
 #include "scf_internal.h"
+
+// No implicit multiply-add contraction: every fused multiply-add below is written out, so the
+// rounding of each expression is fixed by the source and every kernel instantiation (block
+// width, masked or row-walled channel) computes a node bit for bit alike.
+#pragma clang fp contract(off)
 
 namespace scf {
 namespace {
@@ -31,15 +37,41 @@ __device__ __forceinline__ bool solid_at(const Chan& c, int x, int y) {
 __device__ __forceinline__ int dec_wrap(int v, int n) { return v == 0 ? n - 1 : v - 1; }
 __device__ __forceinline__ int inc_wrap(int v, int n) { return v == n - 1 ? 0 : v + 1; }
 
-// Rows 0, 1, ny-2, ny-1 may touch a solid node; all others never do.
+// Rows 0, 1, ny-2, ny-1 may touch a solid row node; all others never do.
 __device__ __forceinline__ bool near_wall(const Chan& c, int y) {
     return c.x1 > c.x0 && (y <= 1 || y >= c.ny - 2);
 }
 
-// Pull the 18 populations streaming into node (x, y) from post-collision buffer g.
+// Solid-neighbourhood code of node (x, y): bit i is set when x + c_i is solid (bit 0: the node
+// itself).  Population i streams in from x - c_i = x + c_opp(i), so it bounces back when bit
+// opp(i) is set; the wall force sums the weighted directions of the set bits 1..8.
+__device__ __forceinline__ uint32_t rows_code(const Chan& c, int x, int y) {
+    const int xm = dec_wrap(x, c.nx), xp = inc_wrap(x, c.nx);
+    const int ym = dec_wrap(y, c.ny), yp = inc_wrap(y, c.ny);
+    const int nxs[9] = {x, xp, x, xm, x, xp, xm, xm, xp};   // x + c_i
+    const int nys[9] = {y, y, yp, y, ym, yp, yp, ym, ym};
+    uint32_t code = 0;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) code |= (uint32_t)solid_at(c, nxs[i], nys[i]) << i;
+    return code;
+}
+
+// Code of a masked channel, precomputed at init (k_codes) as one uint16 per node.
+__device__ __forceinline__ uint32_t mask_code(const Chan& c, const float* ws, int x, int y) {
+    return reinterpret_cast<const uint16_t*>(ws + c.moff)[y * c.pitch + x];
+}
+
+// Either kind; 0 for the rows of a row-walled channel that touch no solid node.
+__device__ __forceinline__ uint32_t node_code(const Chan& c, const float* ws, int x, int y) {
+    if (c.masked) return mask_code(c, ws, x, y);
+    return near_wall(c, y) ? rows_code(c, x, y) : 0u;
+}
+
+// Pull the 18 populations streaming into node (x, y) from post-collision buffer g; with WALLS,
+// `code` (see rows_code) selects the bounce-back directions.
 template <bool WALLS>
 __device__ __forceinline__ void pull18(const float* __restrict__ g, const Chan& c, int x, int y,
-                                       float f[18]) {
+                                       uint32_t code, float f[18]) {
     const int xm = dec_wrap(x, c.nx), xp = inc_wrap(x, c.nx);
     const int ym = dec_wrap(y, c.ny), yp = inc_wrap(y, c.ny);
     const int64_t P = c.plane;
@@ -50,7 +82,7 @@ __device__ __forceinline__ void pull18(const float* __restrict__ g, const Chan& 
     for (int i = 0; i < 9; ++i) {
         int pi = i;
         int idx = sy[i] * c.pitch + sx[i];
-        if (WALLS && i > 0 && solid_at(c, sx[i], sy[i])) {
+        if (WALLS && i > 0 && ((code >> opp[i]) & 1u)) {
             pi = opp[i];
             idx = y * c.pitch + x;
         }
@@ -59,12 +91,15 @@ __device__ __forceinline__ void pull18(const float* __restrict__ g, const Chan& 
     }
 }
 
-__device__ __forceinline__ void pull_node(const float* __restrict__ g, const Chan& c, int x, int y,
-                                          float f[18]) {
-    if (near_wall(c, y))
-        pull18<true>(g, c, x, y, f);
+// Pull of node (x, y) for the per-row kernels; returns the node's solid-neighbourhood code.
+__device__ __forceinline__ uint32_t pull_node(const float* __restrict__ g, const Chan& c,
+                                              const float* ws, int x, int y, float f[18]) {
+    const uint32_t code = node_code(c, ws, x, y);
+    if (c.masked || near_wall(c, y))
+        pull18<true>(g, c, x, y, code, f);
     else
-        pull18<false>(g, c, x, y, f);
+        pull18<false>(g, c, x, y, 0u, f);
+    return code;
 }
 
 // Buffer-descriptor access for the fused step: one descriptor per population buffer (18 planes,
@@ -81,7 +116,7 @@ __device__ __forceinline__ float bload(__amdgpu_buffer_rsrc_t r, int voff, int s
 // As pull18, through a buffer descriptor; Pb = plane size in bytes.
 template <bool WALLS>
 __device__ __forceinline__ void pull18_buf(__amdgpu_buffer_rsrc_t r, int Pb, const Chan& c, int x,
-                                           int y, float f[18]) {
+                                           int y, uint32_t code, float f[18]) {
     const int xm = dec_wrap(x, c.nx), xp = inc_wrap(x, c.nx);
     const int ym = dec_wrap(y, c.ny), yp = inc_wrap(y, c.ny);
     const int sx[9] = {x, xm, x, xp, x, xm, xp, xp, xm};
@@ -93,7 +128,7 @@ __device__ __forceinline__ void pull18_buf(__amdgpu_buffer_rsrc_t r, int Pb, con
         if (WALLS && i > 0) {
             // bounce-back lanes read their own node's opposite direction: fold the plane into
             // the per-lane offset so the scalar offset stays uniform
-            const bool sol = solid_at(c, sx[i], sy[i]);
+            const bool sol = (code >> opp[i]) & 1u;
             const int o = sol ? (y * c.pitch + x) * 4 + opp[i] * Pb : off + i * Pb;
             f[i] = bload(r, o, 0);
             f[9 + i] = bload(r, o, 9 * Pb);
@@ -104,12 +139,23 @@ __device__ __forceinline__ void pull18_buf(__amdgpu_buffer_rsrc_t r, int Pb, con
     }
 }
 
-__device__ __forceinline__ void pull_node_buf(__amdgpu_buffer_rsrc_t r, int Pb, const Chan& c,
-                                              int x, int y, float f[18]) {
-    if (near_wall(c, y))
-        pull18_buf<true>(r, Pb, c, x, y, f);
-    else
-        pull18_buf<false>(r, Pb, c, x, y, f);
+// Pull for the fused step; returns the node's solid-neighbourhood code.  MASK instantiates the
+// masked-channel path (a code load per node); row-walled channels test their rows instead.
+template <bool MASK>
+__device__ __forceinline__ uint32_t pull_node_buf(__amdgpu_buffer_rsrc_t r, int Pb, const Chan& c,
+                                                  const float* ws, int x, int y, float f[18]) {
+    if (MASK && c.masked) {
+        const uint32_t code = mask_code(c, ws, x, y);
+        pull18_buf<true>(r, Pb, c, x, y, code, f);
+        return code;
+    }
+    if (near_wall(c, y)) {
+        const uint32_t code = rows_code(c, x, y);
+        pull18_buf<true>(r, Pb, c, x, y, code, f);
+        return code;
+    }
+    pull18_buf<false>(r, Pb, c, x, y, 0u, f);
+    return 0u;
 }
 
 // Destinations of the post-collision populations: plain global stores or buffer stores, both
@@ -138,16 +184,21 @@ __device__ __forceinline__ float sum9(const float* f) {
     return s;
 }
 
-// sum_i w_i s(x + c_i) c_i over solid neighbours (eq. forcingw without -n_k G_kw).
-__device__ __forceinline__ void wall_sum(const Chan& c, int x, int y, float& sx, float& sy) {
-    const int xm = dec_wrap(x, c.nx), xp = inc_wrap(x, c.nx);
-    const int ym = dec_wrap(y, c.ny), yp = inc_wrap(y, c.ny);
-    const float sE = solid_at(c, xp, y), sW = solid_at(c, xm, y);
-    const float sN = solid_at(c, x, yp), sS = solid_at(c, x, ym);
-    const float sNE = solid_at(c, xp, yp), sNW = solid_at(c, xm, yp);
-    const float sSW = solid_at(c, xm, ym), sSE = solid_at(c, xp, ym);
-    sx = W1 * (sE - sW) + W2 * ((sNE - sSW) + (sSE - sNW));
-    sy = W1 * (sN - sS) + W2 * ((sNE - sSW) + (sNW - sSE));
+// One Cartesian component of sum_i w_i v(x + c_i) c_i: the axis pair (p, m) along the axis and
+// the diagonal pairs (p1, m1), (p2, m2) whose component is +1 / -1.
+__device__ __forceinline__ float link_sum(float p, float m, float p1, float m1, float p2, float m2) {
+    return __builtin_fmaf(W1, p - m, W2 * ((p1 - m1) + (p2 - m2)));
+}
+
+// sum_i w_i s(x + c_i) c_i over solid neighbours (eq. forcingw without -n_k G_kw), from the
+// node's solid-neighbourhood code.
+__device__ __forceinline__ void wall_sum(uint32_t code, float& sx, float& sy) {
+    const float sE = (code >> 1) & 1u, sN = (code >> 2) & 1u;
+    const float sW = (code >> 3) & 1u, sS = (code >> 4) & 1u;
+    const float sNE = (code >> 5) & 1u, sNW = (code >> 6) & 1u;
+    const float sSW = (code >> 7) & 1u, sSE = (code >> 8) & 1u;
+    sx = link_sum(sE, sW, sNE, sSW, sSE, sNW);
+    sy = link_sum(sN, sS, sNE, sSW, sNW, sSE);
 }
 
 // Equilibrium of eqs. feq1-feq3 at (n, u) and BGK relaxation of one component's 9 populations,
@@ -166,24 +217,24 @@ __device__ __forceinline__ float third(float v) { return __builtin_fmaf(v, kThir
 template <class Out>
 __device__ __forceinline__ void relax_store(const float* f, float n, float ux, float uy, float c1,
                                             float om, const Out& out, int qbase) {
-    const float usq6 = (ux * ux + uy * uy) * (1.0f / 6.0f);
+    const float usq6 = __builtin_fmaf(ux, ux, uy * uy) * (1.0f / 6.0f);
     const float up = ux + uy, um = uy - ux;
     const float ox = third(ux), oy = third(uy), op = third(up), oq = third(um);
-    const float ex = 0.5f * ux * ux - usq6, ey = 0.5f * uy * uy - usq6;
-    const float ep = 0.5f * up * up - usq6, eq = 0.5f * um * um - usq6;
+    const float ex = __builtin_fmaf(0.5f * ux, ux, -usq6), ey = __builtin_fmaf(0.5f * uy, uy, -usq6);
+    const float ep = __builtin_fmaf(0.5f * up, up, -usq6), eq = __builtin_fmaf(0.5f * um, um, -usq6);
     const float r = n * c1, r4 = 0.25f * r, n4 = 0.25f * n;
     float D[9];
-    D[1] = (r - f[1]) + n * (ex + ox);
-    D[3] = (r - f[3]) + n * (ex - ox);
-    D[2] = (r - f[2]) + n * (ey + oy);
-    D[4] = (r - f[4]) + n * (ey - oy);
-    D[5] = (r4 - f[5]) + n4 * (ep + op);
-    D[7] = (r4 - f[7]) + n4 * (ep - op);
-    D[6] = (r4 - f[6]) + n4 * (eq + oq);
-    D[8] = (r4 - f[8]) + n4 * (eq - oq);
+    D[1] = __builtin_fmaf(n, ex + ox, r - f[1]);
+    D[3] = __builtin_fmaf(n, ex - ox, r - f[3]);
+    D[2] = __builtin_fmaf(n, ey + oy, r - f[2]);
+    D[4] = __builtin_fmaf(n, ey - oy, r - f[4]);
+    D[5] = __builtin_fmaf(n4, ep + op, r4 - f[5]);
+    D[7] = __builtin_fmaf(n4, ep - op, r4 - f[7]);
+    D[6] = __builtin_fmaf(n4, eq + oq, r4 - f[6]);
+    D[8] = __builtin_fmaf(n4, eq - oq, r4 - f[8]);
     D[0] = -(((D[1] + D[2]) + (D[3] + D[4])) + ((D[5] + D[6]) + (D[7] + D[8])));
 #pragma unroll
-    for (int i = 0; i < 9; ++i) out(qbase + i, f[i] + om * D[i]);
+    for (int i = 0; i < 9; ++i) out(qbase + i, __builtin_fmaf(om, D[i], f[i]));
 }
 
 // Collide one fluid node: f holds its pulled populations (A then B), nA/nB their sums,
@@ -197,13 +248,17 @@ __device__ __forceinline__ void collide_store(const Chan& c, const float f[18], 
     const float jBx = (f[10] - f[12]) + (f[14] - f[15]) + (f[17] - f[16]);
     const float jBy = (f[11] - f[13]) + (f[14] - f[16]) + (f[15] - f[17]);
     // a_k = F_k / n_k: -G sum w n_kbar(x+c) c  -  G_kw sum w s(x+c) c
-    const float aAx = -c.G * sBx - c.gw[0] * swx, aAy = -c.G * sBy - c.gw[0] * swy;
-    const float aBx = -c.G * sAx - c.gw[1] * swx, aBy = -c.G * sAy - c.gw[1] * swy;
-    const float den = c.wm[0] * nA + c.wm[1] * nB;
-    const float Ux = (c.wm[0] * jAx + c.wm[1] * jBx) / den;
-    const float Uy = (c.wm[0] * jAy + c.wm[1] * jBy) / den;
-    relax_store(f, nA, Ux + c.tm[0] * aAx, Uy + c.tm[0] * aAy, c.c1[0], c.omega[0], out, 0);
-    relax_store(f + 9, nB, Ux + c.tm[1] * aBx, Uy + c.tm[1] * aBy, c.c1[1], c.omega[1], out, 9);
+    const float aAx = __builtin_fmaf(-c.G, sBx, -(c.gw[0] * swx));
+    const float aAy = __builtin_fmaf(-c.G, sBy, -(c.gw[0] * swy));
+    const float aBx = __builtin_fmaf(-c.G, sAx, -(c.gw[1] * swx));
+    const float aBy = __builtin_fmaf(-c.G, sAy, -(c.gw[1] * swy));
+    const float den = __builtin_fmaf(c.wm[0], nA, c.wm[1] * nB);
+    const float Ux = __builtin_fmaf(c.wm[0], jAx, c.wm[1] * jBx) / den;
+    const float Uy = __builtin_fmaf(c.wm[0], jAy, c.wm[1] * jBy) / den;
+    relax_store(f, nA, __builtin_fmaf(c.tm[0], aAx, Ux), __builtin_fmaf(c.tm[0], aAy, Uy), c.c1[0],
+                c.omega[0], out, 0);
+    relax_store(f + 9, nB, __builtin_fmaf(c.tm[1], aBx, Ux), __builtin_fmaf(c.tm[1], aBy, Uy),
+                c.c1[1], c.omega[1], out, 9);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -219,7 +274,7 @@ __device__ __forceinline__ void collide_store(const Chan& c, const float f[18], 
 // the rows two chunks share are then pulled by both at about the same time and the second
 // read hits in L2 instead of going back to HBM.
 // ---------------------------------------------------------------------------------------------
-template <int BX>
+template <int BX, bool MASK>
 __global__ void __launch_bounds__(BX)
 k_step_fused(const Chan* __restrict__ chans, const TileDesc* __restrict__ tiles, int ntiles,
              float* __restrict__ ws, int src) {
@@ -239,7 +294,6 @@ k_step_fused(const Chan* __restrict__ chans, const TileDesc* __restrict__ tiles,
         const __amdgpu_buffer_rsrc_t rs = make_rsrc(ws + c.off + (int64_t)src * 18 * c.plane, buf_bytes);
         const __amdgpu_buffer_rsrc_t rd = make_rsrc(ws + c.off + (int64_t)(src ^ 1) * 18 * c.plane, buf_bytes);
         const int Pb = (int)(c.plane * 4);
-        const bool walls = c.x1 > c.x0;
         const int hx = tid == 0 ? (td.xb == 0 ? c.nx - 1 : td.xb - 1)
                                 : (td.xb + w == c.nx ? 0 : td.xb + w);
         const int hslot = tid == 0 ? 0 : w + 1;
@@ -247,15 +301,16 @@ k_step_fused(const Chan* __restrict__ chans, const TileDesc* __restrict__ tiles,
 #pragma unroll
         for (int i = 0; i < 18; ++i) q[i] = 0.0f;
         float qA = 0.0f, qB = 0.0f;
+        uint32_t qcode = 0;
         // first row pulled: the halo below (upward walk) or above (downward walk) the chunk
         int y = down ? (td.ye == c.ny ? 0 : td.ye) : (td.yb == 0 ? c.ny - 1 : td.yb - 1);
         const int niter = td.ye - td.yb + 2;
         for (int it = 0; it < niter; ++it) {
             const int slot = it & 3;
             float p[18];
-            pull_node_buf(rs, Pb, c, x, y, p);
+            const uint32_t code = pull_node_buf<MASK>(rs, Pb, c, ws, x, y, p);
             float nA = 0.0f, nB = 0.0f;
-            if (!(walls && solid_at(c, x, y))) {
+            if (!(code & 1u)) {
                 nA = sum9(p);
                 nB = sum9(p + 9);
             }
@@ -265,9 +320,9 @@ k_step_fused(const Chan* __restrict__ chans, const TileDesc* __restrict__ tiles,
             }
             if (tid < 2) {
                 float h[18];
-                pull_node_buf(rs, Pb, c, hx, y, h);
+                const uint32_t hcode = pull_node_buf<MASK>(rs, Pb, c, ws, hx, y, h);
                 float hA = 0.0f, hB = 0.0f;
-                if (!(walls && solid_at(c, hx, y))) {
+                if (!(hcode & 1u)) {
                     hA = sum9(h);
                     hB = sum9(h + 9);
                 }
@@ -278,7 +333,7 @@ k_step_fused(const Chan* __restrict__ chans, const TileDesc* __restrict__ tiles,
             if (it >= 2 && act) {
                 // the row collided now was pulled one iteration ago
                 const int yc = down ? (y == c.ny - 1 ? 0 : y + 1) : (y == 0 ? c.ny - 1 : y - 1);
-                if (!(walls && solid_at(c, x, yc))) {
+                if (!(qcode & 1u)) {
                     const int s0 = (it - 1) & 3;
                     const int sm = down ? slot : (it - 2) & 3;   // row yc - 1
                     const int sp = down ? (it - 2) & 3 : slot;   // row yc + 1
@@ -291,12 +346,12 @@ k_step_fused(const Chan* __restrict__ chans, const TileDesc* __restrict__ tiles,
                     const float BN = sn[1][sp][l], BS = sn[1][sm][l];
                     const float BNE = sn[1][sp][l + 1], BNW = sn[1][sp][l - 1];
                     const float BSW = sn[1][sm][l - 1], BSE = sn[1][sm][l + 1];
-                    const float sAx = W1 * (AE - AW) + W2 * ((ANE - ASW) + (ASE - ANW));
-                    const float sAy = W1 * (AN - AS) + W2 * ((ANE - ASW) + (ANW - ASE));
-                    const float sBx = W1 * (BE - BW) + W2 * ((BNE - BSW) + (BSE - BNW));
-                    const float sBy = W1 * (BN - BS) + W2 * ((BNE - BSW) + (BNW - BSE));
+                    const float sAx = link_sum(AE, AW, ANE, ASW, ASE, ANW);
+                    const float sAy = link_sum(AN, AS, ANE, ASW, ANW, ASE);
+                    const float sBx = link_sum(BE, BW, BNE, BSW, BSE, BNW);
+                    const float sBy = link_sum(BN, BS, BNE, BSW, BNW, BSE);
                     float swx = 0.0f, swy = 0.0f;
-                    if (near_wall(c, yc)) wall_sum(c, x, yc, swx, swy);
+                    if (qcode) wall_sum(qcode, swx, swy);
                     collide_store(c, q, qA, qB, sAx, sAy, sBx, sBy, swx, swy,
                                   BufferOut{rd, Pb, (yc * c.pitch + x) * 4});
                 }
@@ -305,6 +360,7 @@ k_step_fused(const Chan* __restrict__ chans, const TileDesc* __restrict__ tiles,
             for (int i = 0; i < 18; ++i) q[i] = p[i];
             qA = nA;
             qB = nB;
+            qcode = code;
             y = down ? (y == 0 ? c.ny - 1 : y - 1) : (y == c.ny - 1 ? 0 : y + 1);
         }
         __syncthreads();
@@ -323,12 +379,11 @@ k_density(const Chan* __restrict__ chans, const RowRef* __restrict__ rows, float
     const Chan c = chans[r.chan];
     const float* __restrict__ g = ws + c.off + (int64_t)src * 18 * c.plane;
     float* __restrict__ dn = ws + c.off + 36 * c.plane;
-    const bool walls = c.x1 > c.x0;
     for (int x = threadIdx.x; x < c.nx; x += kRowThreads) {
         float p[18];
-        pull_node(g, c, x, r.y, p);
+        const uint32_t code = pull_node(g, c, ws, x, r.y, p);
         float nA = 0.0f, nB = 0.0f;
-        if (!(walls && solid_at(c, x, r.y))) {
+        if (!(code & 1u)) {
             nA = sum9(p);
             nB = sum9(p + 9);
         }
@@ -346,14 +401,13 @@ k_collide(const Chan* __restrict__ chans, const RowRef* __restrict__ rows, float
     float* __restrict__ d = ws + c.off + (int64_t)(src ^ 1) * 18 * c.plane;
     const float* __restrict__ nA_f = ws + c.off + 36 * c.plane;
     const float* __restrict__ nB_f = nA_f + c.plane;
-    const bool walls = c.x1 > c.x0;
     const int y = r.y;
-    if (walls && (y == 0 || y == c.ny - 1) && c.x0 == 0 && c.x1 == c.nx) return;
+    if (!c.masked && c.x1 > c.x0 && (y == 0 || y == c.ny - 1) && c.x0 == 0 && c.x1 == c.nx) return;
     const int ym = dec_wrap(y, c.ny), yp = inc_wrap(y, c.ny);
     for (int x = threadIdx.x; x < c.nx; x += kRowThreads) {
-        if (walls && solid_at(c, x, y)) continue;
+        if (node_code(c, ws, x, y) & 1u) continue;
         float p[18];
-        pull_node(g, c, x, y, p);
+        const uint32_t code = pull_node(g, c, ws, x, y, p);
         const float nA = sum9(p), nB = sum9(p + 9);
         const int xm = dec_wrap(x, c.nx), xp = inc_wrap(x, c.nx);
         const int r0 = y * c.pitch, rm = ym * c.pitch, rp = yp * c.pitch;
@@ -361,12 +415,12 @@ k_collide(const Chan* __restrict__ chans, const RowRef* __restrict__ rows, float
         const float ANE = nA_f[rp + xp], ANW = nA_f[rp + xm], ASW = nA_f[rm + xm], ASE = nA_f[rm + xp];
         const float BE = nB_f[r0 + xp], BW = nB_f[r0 + xm], BN = nB_f[rp + x], BS = nB_f[rm + x];
         const float BNE = nB_f[rp + xp], BNW = nB_f[rp + xm], BSW = nB_f[rm + xm], BSE = nB_f[rm + xp];
-        const float sAx = W1 * (AE - AW) + W2 * ((ANE - ASW) + (ASE - ANW));
-        const float sAy = W1 * (AN - AS) + W2 * ((ANE - ASW) + (ANW - ASE));
-        const float sBx = W1 * (BE - BW) + W2 * ((BNE - BSW) + (BSE - BNW));
-        const float sBy = W1 * (BN - BS) + W2 * ((BNE - BSW) + (BNW - BSE));
+        const float sAx = link_sum(AE, AW, ANE, ASW, ASE, ANW);
+        const float sAy = link_sum(AN, AS, ANE, ASW, ANW, ASE);
+        const float sBx = link_sum(BE, BW, BNE, BSW, BSE, BNW);
+        const float sBy = link_sum(BN, BS, BNE, BSW, BNW, BSE);
         float swx = 0.0f, swy = 0.0f;
-        if (near_wall(c, y)) wall_sum(c, x, y, swx, swy);
+        if (code) wall_sum(code, swx, swy);
         collide_store(c, p, nA, nB, sAx, sAy, sBx, sBy, swx, swy, GlobalOut{d, c.plane, r0 + x});
     }
 }
@@ -391,7 +445,8 @@ k_init(const Chan* __restrict__ chans, const RowRef* __restrict__ rows, float* _
         const int xm = dec_wrap(x, c.nx), xp = inc_wrap(x, c.nx);
         const int nxs[9] = {x, xp, x, xm, x, xp, xm, xm, xp};   // x + c_i
         const int nys[9] = {y, y, yp, y, ym, yp, yp, ym, ym};
-        const bool solid = solid_at(c, x, y);
+        const uint32_t code = node_code(c, ws, x, y);
+        const bool solid = code & 1u;
         const int idx = y * c.pitch + x;
         for (int k = 0; k < 2; ++k) {
             const double* rk = rho + k * cells;
@@ -400,7 +455,7 @@ k_init(const Chan* __restrict__ chans, const RowRef* __restrict__ rows, float* _
             for (int i = 0; i < 9; ++i) {
                 const float e = i == 0 ? c.c0[k] : (i < 5 ? c.c1[k] : 0.25f * c.c1[k]);
                 double nn = n0;
-                if (!solid_at(c, nxs[i], nys[i]))
+                if (!((code >> i) & 1u))
                     nn = rk[(int64_t)nys[i] * c.nx + nxs[i]] * (double)c.inv_m[k];
                 g[(k * 9 + i) * P + idx] = solid ? 0.0f : e * (float)nn;
             }
@@ -418,8 +473,7 @@ k_pull_out(const Chan* __restrict__ chans, const RowRef* __restrict__ rows, floa
     float* __restrict__ o = ws + c.off + (int64_t)(src ^ 1) * 18 * c.plane;
     for (int x = threadIdx.x; x < c.nx; x += kRowThreads) {
         float p[18];
-        pull_node(g, c, x, r.y, p);
-        const bool solid = solid_at(c, x, r.y);
+        const bool solid = pull_node(g, c, ws, x, r.y, p) & 1u;
 #pragma unroll
         for (int i = 0; i < 18; ++i) o[i * c.plane + r.y * c.pitch + x] = solid ? 0.0f : p[i];
     }
@@ -471,9 +525,9 @@ k_obs_rows(const Chan* __restrict__ chans, const RowRef* __restrict__ rows, floa
     int bad = 0;
     for (int x = threadIdx.x; x < c.nx; x += kRowThreads) {
         float p[18];
-        pull_node(g, c, x, r.y, p);
+        const uint32_t code = pull_node(g, c, ws, x, r.y, p);
         float nA = 0.0f, nB = 0.0f;
-        if (!solid_at(c, x, r.y)) {
+        if (!(code & 1u)) {
             nA = sum9(p);
             nB = sum9(p + 9);
             mA += (double)nA;
@@ -573,27 +627,57 @@ __global__ void k_bump(int32_t* counter) {
 }
 
 template <int BX>
-hipError_t launch_fused_bx(const Chan* chans, const TileDesc* tiles, int ntiles, int grid,
-                           float* ws, int src, hipStream_t s) {
+hipError_t launch_fused_bx(bool masked, const Chan* chans, const TileDesc* tiles, int ntiles,
+                           int grid, float* ws, int src, hipStream_t s) {
     const int g = grid > 0 ? min(grid, ntiles) : ntiles;
-    hipLaunchKernelGGL(k_step_fused<BX>, dim3(g), dim3(BX), 0, s, chans, tiles, ntiles, ws, src);
+    if (masked)
+        hipLaunchKernelGGL((k_step_fused<BX, true>), dim3(g), dim3(BX), 0, s, chans, tiles, ntiles, ws, src);
+    else
+        hipLaunchKernelGGL((k_step_fused<BX, false>), dim3(g), dim3(BX), 0, s, chans, tiles, ntiles, ws, src);
     return hipGetLastError();
+}
+
+// Solid-neighbourhood codes of masked channels from the staged uint8 mask (ny*nx bytes after
+// the two FP64 fields in population buffer 1).  Row-walled channels are skipped.
+__global__ void __launch_bounds__(kRowThreads)
+k_codes(const Chan* __restrict__ chans, const RowRef* __restrict__ rows, float* __restrict__ ws) {
+    const RowRef r = rows[blockIdx.x];
+    const Chan c = chans[r.chan];
+    if (!c.masked) return;
+    const int64_t cells = (int64_t)c.nx * c.ny;
+    const uint8_t* __restrict__ m =
+        reinterpret_cast<const uint8_t*>(ws + c.off + 18 * c.plane) + 16 * cells;
+    uint16_t* __restrict__ codes = reinterpret_cast<uint16_t*>(ws + c.moff);
+    const int y = r.y;
+    const int ym = dec_wrap(y, c.ny), yp = inc_wrap(y, c.ny);
+    for (int x = threadIdx.x; x < c.nx; x += kRowThreads) {
+        const int xm = dec_wrap(x, c.nx), xp = inc_wrap(x, c.nx);
+        const int nxs[9] = {x, xp, x, xm, x, xp, xm, xm, xp};   // x + c_i
+        const int nys[9] = {y, y, yp, y, ym, yp, yp, ym, ym};
+        uint32_t code = 0;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) code |= (uint32_t)(m[(int64_t)nys[i] * c.nx + nxs[i]] != 0) << i;
+        codes[y * c.pitch + x] = (uint16_t)code;
+    }
 }
 
 }  // namespace
 
 hipError_t launch_init(const Chan* chans, const RowRef* rows, int nrows, float* ws, hipStream_t s) {
+    hipLaunchKernelGGL(k_codes, dim3(nrows), dim3(kRowThreads), 0, s, chans, rows, ws);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_init, dim3(nrows), dim3(kRowThreads), 0, s, chans, rows, ws);
     return hipGetLastError();
 }
 
-hipError_t launch_step_fused(int bx, const Chan* chans, const TileDesc* tiles, int ntiles, int grid,
-                             float* ws, int src, hipStream_t s) {
+hipError_t launch_step_fused(int bx, bool masked, const Chan* chans, const TileDesc* tiles,
+                             int ntiles, int grid, float* ws, int src, hipStream_t s) {
     switch (bx) {
-        case 64: return launch_fused_bx<64>(chans, tiles, ntiles, grid, ws, src, s);
-        case 128: return launch_fused_bx<128>(chans, tiles, ntiles, grid, ws, src, s);
-        case 256: return launch_fused_bx<256>(chans, tiles, ntiles, grid, ws, src, s);
-        case 512: return launch_fused_bx<512>(chans, tiles, ntiles, grid, ws, src, s);
+        case 64: return launch_fused_bx<64>(masked, chans, tiles, ntiles, grid, ws, src, s);
+        case 128: return launch_fused_bx<128>(masked, chans, tiles, ntiles, grid, ws, src, s);
+        case 256: return launch_fused_bx<256>(masked, chans, tiles, ntiles, grid, ws, src, s);
+        case 512: return launch_fused_bx<512>(masked, chans, tiles, ntiles, grid, ws, src, s);
         default: return hipErrorInvalidValue;
     }
 }

@@ -40,6 +40,23 @@ int pitch_of(int nx) { return (nx + 63) / 64 * 64; }
 constexpr int kMaxRowsPerGeom = 1 << 20;
 constexpr int kPlanesPerChannel = 38;   // 2 x 18 population planes + 2 density planes
 
+// Float planes of one channel: populations and densities, plus one for the uint16 codes of a
+// solid mask.
+int planes_of(const scf_geometry& g) { return kPlanesPerChannel + (g.solid ? 1 : 0); }
+
+// FNV-1a of the 0/1 solid mask (0 when the channel has none); identifies the geometry in
+// checkpoints.
+uint64_t mask_hash(const scf_geometry& g) {
+    if (!g.solid) return 0;
+    uint64_t h = 1469598103934665603ull;
+    const size_t n = (size_t)g.nx * g.ny;
+    for (size_t i = 0; i < n; ++i) {
+        h ^= (uint64_t)(g.solid[i] != 0);
+        h *= 1099511628211ull;
+    }
+    return h | 1;
+}
+
 bool geom_ok(const scf_geometry* g, std::string* why) {
     if (!g) { *why = "geometry is NULL"; return false; }
     if (g->nx < 3 || g->ny < 3 || g->nx >= kMaxRowsPerGeom || g->ny >= kMaxRowsPerGeom) {
@@ -93,7 +110,7 @@ Layout plan(int nchan, const scf_geometry* g, int max_samples) {
     L.counter = off; off = align_up(off + 256, 256);
     for (int c = 0; c < nchan; ++c) {
         L.chan_off.push_back(off);
-        off = align_up(off + sizeof(float) * kPlanesPerChannel * (size_t)g[c].ny * pitch_of(g[c].nx), 256);
+        off = align_up(off + sizeof(float) * planes_of(g[c]) * (size_t)g[c].ny * pitch_of(g[c].nx), 256);
     }
     L.total = off;
     return L;
@@ -106,6 +123,8 @@ scf::Chan make_chan(const scf_geometry& g, const scf_params& p, size_t byte_off,
     c.row_base = row_base;
     c.off = (int64_t)(byte_off / sizeof(float));
     c.plane = (int64_t)g.ny * c.pitch;
+    c.masked = g.solid ? 1 : 0;
+    c.moff = c.off + (int64_t)kPlanesPerChannel * c.plane;
     c.G = (float)p.G;
     for (int k = 0; k < 2; ++k) {
         c.gw[k] = (float)p.gw[k];
@@ -128,7 +147,9 @@ int set_error(int code, const std::string& msg) { return fail(code, msg); }
 
 struct Engine {
     int nchan = 0;
-    std::vector<scf_geometry> geom;
+    std::vector<scf_geometry> geom;   // copies with the mask pointer cleared (masks are not kept)
+    std::vector<uint64_t> mhash;      // mask_hash per channel
+    bool any_masked = false;
     std::vector<scf_params> prm;
     std::vector<scf::Chan> chans;
     Layout lay;
@@ -226,7 +247,7 @@ struct Engine {
     hipError_t launch_step(hipStream_t s, int src) const {
         if (variant == SCF_VARIANT_TWO_KERNEL)
             return scf::launch_step_two_kernel(d_chans(), d_rows(), lay.nrows, base(), src, s);
-        return scf::launch_step_fused(bx, d_chans(), d_tiles(), ntiles, grid, base(), src, s);
+        return scf::launch_step_fused(bx, any_masked, d_chans(), d_tiles(), ntiles, grid, base(), src, s);
     }
 
     hipError_t launch_obs(hipStream_t s, int record) const {
@@ -333,6 +354,13 @@ struct Engine {
         if (max_samp < 1) return fail(SCF_EINVAL, "max_samples must be >= 1");
         nchan = nch;
         geom.assign(g, g + nch);
+        mhash.clear();
+        any_masked = false;
+        for (int c = 0; c < nch; ++c) {
+            mhash.push_back(mask_hash(g[c]));
+            any_masked = any_masked || g[c].solid != nullptr;
+            geom[c].solid = nullptr;
+        }
         prm.assign(p, p + nch);
         lay = plan(nch, g, max_samp);
         if (bytes < lay.total)
@@ -352,13 +380,17 @@ struct Engine {
         HIP_TRY(hipMemcpyAsync(d_chans(), chans.data(), sizeof(scf::Chan) * nch, hipMemcpyHostToDevice, stream));
         HIP_TRY(hipMemcpyAsync(d_rows(), rows.data(), sizeof(scf::RowRef) * rows.size(), hipMemcpyHostToDevice, stream));
         HIP_TRY(hipMemsetAsync(d_counter(), 0, 256, stream));
-        // stage FP64 fields in population buffer 1 of each channel, then build buffer 0
+        // stage the FP64 fields (and the mask bytes) in population buffer 1 of each channel,
+        // then build the mask codes and buffer 0
         for (int c = 0; c < nch; ++c) {
             const size_t cells = (size_t)g[c].nx * g[c].ny;
             char* stage = ws + lay.chan_off[c] + sizeof(float) * 18 * chans[c].plane;
             HIP_TRY(hipMemcpyAsync(stage, rhoA[c], sizeof(double) * cells, hipMemcpyHostToDevice, stream));
             HIP_TRY(hipMemcpyAsync(stage + sizeof(double) * cells, rhoB[c], sizeof(double) * cells,
                                    hipMemcpyHostToDevice, stream));
+            if (g[c].solid)
+                HIP_TRY(hipMemcpyAsync(stage + 2 * sizeof(double) * cells, g[c].solid, cells,
+                                       hipMemcpyHostToDevice, stream));
         }
         HIP_TRY(scf::launch_init(d_chans(), d_rows(), lay.nrows, base(), stream));
         cur = 0;
@@ -557,11 +589,16 @@ namespace {
 struct CkptHeader {
     char magic[8];
     int32_t version, nchan;
-    scf_geometry geom;
+    int32_t nx, ny, x0, x1;
+    uint64_t mask;   // mask_hash of the geometry
     scf_params params;
     int64_t t;
     int64_t floats;
 };
+
+bool same_geometry(const CkptHeader& h, const scf_geometry& g, uint64_t mhash) {
+    return h.nx == g.nx && h.ny == g.ny && h.x0 == g.x0 && h.x1 == g.x1 && h.mask == mhash;
+}
 }  // namespace
 
 int scf_save(scf_ctx* ctx, const char* path) {
@@ -569,10 +606,14 @@ int scf_save(scf_ctx* ctx, const char* path) {
     Engine& e = ctx->e;
     CkptHeader h;
     std::memset(&h, 0, sizeof h);
-    std::memcpy(h.magic, "SCFCKPT1", 8);
-    h.version = 1;
+    std::memcpy(h.magic, "SCFCKPT2", 8);
+    h.version = 2;
     h.nchan = 1;
-    h.geom = e.geom[0];
+    h.nx = e.geom[0].nx;
+    h.ny = e.geom[0].ny;
+    h.x0 = e.geom[0].x0;
+    h.x1 = e.geom[0].x1;
+    h.mask = e.mhash[0];
     h.params = e.prm[0];
     h.t = e.t;
     h.floats = 18 * e.chans[0].plane;
@@ -594,8 +635,8 @@ int scf_load(scf_ctx* ctx, const char* path) {
     FILE* f = std::fopen(path, "rb");
     if (!f) return fail(SCF_EINVAL, std::string("cannot open ") + path);
     CkptHeader h;
-    bool ok = std::fread(&h, sizeof h, 1, f) == 1 && std::memcmp(h.magic, "SCFCKPT1", 8) == 0 &&
-              h.version == 1 && h.nchan == 1 && std::memcmp(&h.geom, &e.geom[0], sizeof h.geom) == 0 &&
+    bool ok = std::fread(&h, sizeof h, 1, f) == 1 && std::memcmp(h.magic, "SCFCKPT2", 8) == 0 &&
+              h.version == 2 && h.nchan == 1 && same_geometry(h, e.geom[0], e.mhash[0]) &&
               std::memcmp(&h.params, &e.prm[0], sizeof h.params) == 0 &&
               h.floats == 18 * e.chans[0].plane;
     std::vector<float> buf;

@@ -15,8 +15,18 @@ from . import _lib as L
 from .inputs import Case, Geometry, Params
 
 
-def _geom(g: Geometry) -> L.scf_geometry:
-    return L.scf_geometry(g.nx, g.ny, g.x0, g.x1)
+def _mask(g: Geometry) -> Optional[np.ndarray]:
+    if g.solid is None:
+        return None
+    m = np.ascontiguousarray(np.asarray(g.solid) != 0, dtype=np.uint8)
+    if m.shape != (g.ny, g.nx):
+        raise ValueError("solid mask must have shape (ny, nx)")
+    return m
+
+
+def _geom(g: Geometry, mask: Optional[np.ndarray] = None) -> L.scf_geometry:
+    # `mask` (from _mask) must stay alive until the init call has returned
+    return L.scf_geometry(g.nx, g.ny, g.x0, g.x1, None if mask is None else mask.ctypes.data)
 
 
 def _params(p: Params) -> L.scf_params:
@@ -52,7 +62,8 @@ class Channel:
     def __init__(self, geom: Geometry, params: Params, rhoA: np.ndarray, rhoB: np.ndarray,
                  device="cuda:0", stream: Optional[torch.cuda.Stream] = None):
         self.geom, self.params = geom, params
-        self._g, self._p = _geom(geom), _params(params)
+        self._m = _mask(geom)
+        self._g, self._p = _geom(geom, self._m), _params(params)
         nbytes = L.scf_workspace_bytes(C.byref(self._g))
         if nbytes == 0:
             raise L.ScfError(L.SCF_EINVAL, f"invalid geometry {geom}")
@@ -135,7 +146,8 @@ class Batch:
                  stream: Optional[torch.cuda.Stream] = None):
         self.cases = list(cases)
         n = len(self.cases)
-        self._g = (L.scf_geometry * n)(*[_geom(c.geom) for c in self.cases])
+        self._m = [_mask(c.geom) for c in self.cases]
+        self._g = (L.scf_geometry * n)(*[_geom(c.geom, m) for c, m in zip(self.cases, self._m)])
         self._p = (L.scf_params * n)(*[_params(c.params) for c in self.cases])
         self.max_samples = int(max_samples)
         self.sample_every = int(sample_every)

@@ -125,7 +125,7 @@ def _state(ch):
 
 @pytest.mark.parametrize("bx,cy,order", [(64, 8, 0), (64, 1 << 30, 0), (128, 5, 0), (256, 64, 0),
                                          (256, 1, 0), (128, 23, 0), (64, 4, 1), (256, 7, 1), (128, 1, 1),
-                                         (64, 3, 2), (256, 16, 3), (128, 1, 3)])
+                                         (64, 3, 2), (256, 16, 3), (128, 1, 3), (512, 8, 1), (512, 1 << 30, 2)])
 def test_tile_shapes_bitwise(scf, bx, cy, order):
     case = inputs.capillary_small(seed=2)
     _say(f"case: tile shape bx={bx} cy={cy} order={order}")
