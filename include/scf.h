@@ -95,6 +95,10 @@ typedef struct {
                              band), optionally | SCF_ORDER_XCD (each of the 8 XCDs takes a
                              contiguous eighth of that order instead of every 8th tile) */
     int32_t graph_steps;  /* steps per captured HIP graph, 0 = launch every step directly */
+    int32_t fuse;         /* time steps per pass of the fused step: 1, or 2 (temporal blocking:
+                             each launch advances two steps, its tiles are bx - 4 columns wide and
+                             the intermediate populations stay on chip; an odd remainder of a
+                             step count is done by one single step).  Same results bit for bit. */
 } scf_tile;
 
 enum { SCF_ORDER_STRIPS = 0, SCF_ORDER_BANDS = 1, SCF_ORDER_XCD = 2 };
@@ -143,15 +147,17 @@ int scf_get_populations(scf_ctx* ctx, double* f);
 int scf_set_variant(scf_ctx* ctx, int32_t variant);
 
 /* Set the launch schedule of the fused step: tiles of bx columns by cy rows (every other tile
- * of a strip walks its rows downward), taken by the blocks of one launch in the given order.
- * Schedules change only the order of work, never the result.
- * Invalidates captured graphs.  Errors: SCF_EINVAL. */
+ * of a strip walks its rows downward), taken by the blocks of one launch in the given order,
+ * and one or two time steps per launch (fuse).  Schedules change only the order of work, never
+ * the result.  Invalidates captured graphs.  Errors: SCF_EINVAL (bx not 64/128/256/512,
+ * cy < 1, unknown order, graph_steps < 0, fuse not 1 or 2). */
 int scf_set_tile(scf_ctx* ctx, const scf_tile* tile);
 int scf_get_tile(const scf_ctx* ctx, scf_tile* tile);
 
-/* Time candidate schedules (bx, cy, order) for `trial_steps` launches each and keep the
- * fastest.  Every trial launch reads the resident buffer and writes the idle one, so the state
- * is unchanged.  The graph length is kept.  Writes the chosen schedule to *chosen if non-NULL. */
+/* Time candidate schedules (bx, cy, order, fuse) for `trial_steps` launches each and keep the
+ * fastest per time step.  Every trial launch reads the resident buffer and writes the idle one,
+ * so the state is unchanged.  The graph length is kept.  Writes the chosen schedule to *chosen
+ * if non-NULL. */
 int scf_autotune(scf_ctx* ctx, int32_t trial_steps, scf_tile* chosen);
 
 /* Elapsed time step count of the context. */

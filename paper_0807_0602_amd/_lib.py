@@ -41,10 +41,12 @@ class scf_obs(C.Structure):
 
 
 class scf_tile(C.Structure):
-    _fields_ = [("bx", C.c_int32), ("cy", C.c_int32), ("order", C.c_int32), ("graph_steps", C.c_int32)]
+    _fields_ = [("bx", C.c_int32), ("cy", C.c_int32), ("order", C.c_int32), ("graph_steps", C.c_int32),
+                ("fuse", C.c_int32)]
 
     def as_dict(self) -> dict:
-        return {"bx": self.bx, "cy": self.cy, "order": self.order, "graph_steps": self.graph_steps}
+        return {"bx": self.bx, "cy": self.cy, "order": self.order, "graph_steps": self.graph_steps,
+                "fuse": self.fuse}
 
 
 SCF_ORDER_STRIPS, SCF_ORDER_BANDS, SCF_ORDER_XCD = 0, 1, 2

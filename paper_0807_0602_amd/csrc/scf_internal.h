@@ -62,6 +62,9 @@ struct TileDesc {
 hipError_t launch_init(const Chan* chans, const RowRef* rows, int nrows, float* ws, hipStream_t s);
 hipError_t launch_step_fused(int bx, bool masked, const Chan* chans, const TileDesc* tiles,
                              int ntiles, int grid, float* ws, int src, hipStream_t s);
+// Two time steps in one pass; the tiles' strips are bx - 4 columns wide (see k_step_fused2).
+hipError_t launch_step_fused2(int bx, bool masked, const Chan* chans, const TileDesc* tiles,
+                              int ntiles, int grid, float* ws, int src, hipStream_t s);
 hipError_t launch_step_two_kernel(const Chan* chans, const RowRef* rows, int nrows, float* ws,
                                   int src, hipStream_t s);
 hipError_t launch_observe(const Chan* chans, const RowRef* rows, int nrows, int nchan, float* ws,

@@ -368,6 +368,246 @@ k_step_fused(const Chan* __restrict__ chans, const TileDesc* __restrict__ tiles,
 }
 
 // ---------------------------------------------------------------------------------------------
+// Two time steps per pass (temporal blocking).  A block of BX lanes owns the output columns
+// [xb, xb + w), w <= BX - 4, and rows [yb, ye).  Stage 1 is the single step above on the wider
+// window [xb - 2, xb + w + 2) (lane = column + 2 - xb), with the two density-halo columns
+// xb - 3 and xb + w + 2 pulled by lanes 0 and 1; its post-collision values f*(t) never leave
+// the chip.  Stage 2 streams them: the x part by whole-wave lane shifts (DPP; the lanes at a
+// wave's edge take their neighbour's values through LDS), the y part by keeping the shifted
+// rows in registers; bounce-back uses the node's own unshifted f*(t).  Stage 2 then forms
+// n(t+1) into a second density ring and collides, storing f*(t+1).  Rows lag: iteration k
+// pulls row yb-3+k, stage 1 collides row yb-4+k, stage 2 pulls row yb-5+k and collides and
+// stores row yb-6+k.  Three barriers per row: after the stage-1 densities, after the edge
+// values, after the stage-2 densities.  Each node is computed with exactly the arithmetic of
+// the single step, so two stages equal two single steps bit for bit.
+// ---------------------------------------------------------------------------------------------
+struct RegOut {
+    float* r;
+    __device__ __forceinline__ void operator()(int q, float v) const { r[q] = v; }
+};
+
+__device__ __forceinline__ int wrap_mod(int v, int n) {
+    v %= n;
+    return v < 0 ? v + n : v;
+}
+
+// Whole-wave lane shifts: lane l receives the value of lane l - 1 (from_left) or l + 1
+// (from_right); the lane without a source keeps its own value.  Every lane must be active.
+__device__ __forceinline__ float lane_from_left(float v) {
+    const int i = __builtin_bit_cast(int, v);
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(i, i, 0x138, 0xf, 0xf, false));
+}
+__device__ __forceinline__ float lane_from_right(float v) {
+    const int i = __builtin_bit_cast(int, v);
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(i, i, 0x130, 0xf, 0xf, false));
+}
+
+// Neighbour sums sum_i w_i n_k(x + c_i) c_i of both components at slot l of three density
+// rows (m: y - 1, o: y, p: y + 1).
+__device__ __forceinline__ void ring_sums(const float* Am, const float* Ao, const float* Ap,
+                                          const float* Bm, const float* Bo, const float* Bp, int l,
+                                          float& sAx, float& sAy, float& sBx, float& sBy) {
+    sAx = link_sum(Ao[l + 1], Ao[l - 1], Ap[l + 1], Am[l - 1], Am[l + 1], Ap[l - 1]);
+    sAy = link_sum(Ap[l], Am[l], Ap[l + 1], Am[l - 1], Ap[l - 1], Am[l + 1]);
+    sBx = link_sum(Bo[l + 1], Bo[l - 1], Bp[l + 1], Bm[l - 1], Bm[l + 1], Bp[l - 1]);
+    sBy = link_sum(Bp[l], Bm[l], Bp[l + 1], Bm[l - 1], Bp[l - 1], Bm[l + 1]);
+}
+
+template <int BX, bool MASK>
+__global__ void __launch_bounds__(BX)
+k_step_fused2(const Chan* __restrict__ chans, const TileDesc* __restrict__ tiles, int ntiles,
+              float* __restrict__ ws, int src) {
+    constexpr int NW = BX / 64;
+    __shared__ float r1[2][3][BX + 2];   // n(t): slot 0 and w + 5 are the halo columns
+    __shared__ float r2[2][3][BX];       // n(t + 1)
+    __shared__ float eR[NW][6];          // lane 63 of each wave: f*_1, f*_5, f*_8 (A, B)
+    __shared__ float eL[NW][6];          // lane 0 of each wave:  f*_3, f*_6, f*_7 (A, B)
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wv = tid >> 6;
+    const int opp[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+    for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const TileDesc td = tiles[t];
+        if (td.ye <= td.yb) continue;
+        const Chan c = chans[td.chan];
+        const int w = min(BX - 4, c.nx - td.xb);
+        const bool in1 = tid < w + 4;
+        const bool in2 = tid >= 2 && tid < w + 2;
+        const int x = wrap_mod(td.xb - 2 + min(tid, w + 3), c.nx);
+        const int64_t buf_bytes = (int64_t)18 * c.plane * 4;
+        const __amdgpu_buffer_rsrc_t rs = make_rsrc(ws + c.off + (int64_t)src * 18 * c.plane, buf_bytes);
+        const __amdgpu_buffer_rsrc_t rd = make_rsrc(ws + c.off + (int64_t)(src ^ 1) * 18 * c.plane, buf_bytes);
+        const int Pb = (int)(c.plane * 4);
+        const int hx = wrap_mod(tid == 0 ? td.xb - 3 : td.xb + w + 2, c.nx);
+        const int hslot = tid == 0 ? 0 : w + 5;
+        // stage 1: pulled row awaiting collision
+        float q[18];
+        float qA = 0.0f, qB = 0.0f;
+        uint32_t qcode = 0;
+        // stage 2: shifted f*(t) of the last two stage-1 rows (dirs 0,1,3,2,5,6 and 2,5,6 per
+        // component), own unshifted f*(t) of the last row, pulled row awaiting collision
+        float gm1[12], gm2[6], uf[18], q2[18];
+        float q2A = 0.0f, q2B = 0.0f;
+        uint32_t q2code = 0;
+#pragma unroll
+        for (int i = 0; i < 18; ++i) q[i] = uf[i] = q2[i] = 0.0f;
+#pragma unroll
+        for (int i = 0; i < 12; ++i) gm1[i] = 0.0f;
+#pragma unroll
+        for (int i = 0; i < 6; ++i) gm2[i] = 0.0f;
+        const int niter = td.ye - td.yb + 6;
+        for (int k = 0; k < niter; ++k) {
+            const int s0 = k % 3, s1 = (k + 2) % 3, s2 = (k + 1) % 3;   // iterations k, k-1, k-2
+            // A: stage-1 pull of row a, densities n(t) into r1
+            const int a = wrap_mod(td.yb - 3 + k, c.ny);
+            float p[18];
+            const uint32_t code = pull_node_buf<MASK>(rs, Pb, c, ws, x, a, p);
+            float nA = 0.0f, nB = 0.0f;
+            if (!(code & 1u)) {
+                nA = sum9(p);
+                nB = sum9(p + 9);
+            }
+            if (in1) {
+                r1[0][s0][tid + 1] = nA;
+                r1[1][s0][tid + 1] = nB;
+            }
+            if (tid < 2) {
+                float h[18];
+                const uint32_t hcode = pull_node_buf<MASK>(rs, Pb, c, ws, hx, a, h);
+                float hA = 0.0f, hB = 0.0f;
+                if (!(hcode & 1u)) {
+                    hA = sum9(h);
+                    hB = sum9(h + 9);
+                }
+                r1[0][s0][hslot] = hA;
+                r1[1][s0][hslot] = hB;
+            }
+            __syncthreads();
+            // B: stage-1 collision of row a - 1 into registers, then the x part of streaming
+            float fs[18];
+#pragma unroll
+            for (int i = 0; i < 18; ++i) fs[i] = 0.0f;
+            if (k >= 2 && in1 && !(qcode & 1u)) {
+                float sAx, sAy, sBx, sBy;
+                ring_sums(r1[0][s2], r1[0][s1], r1[0][s0], r1[1][s2], r1[1][s1], r1[1][s0], tid + 1,
+                          sAx, sAy, sBx, sBy);
+                float swx = 0.0f, swy = 0.0f;
+                if (qcode) wall_sum(qcode, swx, swy);
+                collide_store(c, q, qA, qB, sAx, sAy, sBx, sBy, swx, swy, RegOut{fs});
+            }
+            float g[18];
+#pragma unroll
+            for (int o = 0; o < 18; o += 9) {
+                g[o + 0] = fs[o + 0];
+                g[o + 2] = fs[o + 2];
+                g[o + 4] = fs[o + 4];
+                g[o + 1] = lane_from_left(fs[o + 1]);
+                g[o + 5] = lane_from_left(fs[o + 5]);
+                g[o + 8] = lane_from_left(fs[o + 8]);
+                g[o + 3] = lane_from_right(fs[o + 3]);
+                g[o + 6] = lane_from_right(fs[o + 6]);
+                g[o + 7] = lane_from_right(fs[o + 7]);
+            }
+            if (lane == 63) {
+                eR[wv][0] = fs[1]; eR[wv][1] = fs[5]; eR[wv][2] = fs[8];
+                eR[wv][3] = fs[10]; eR[wv][4] = fs[14]; eR[wv][5] = fs[17];
+            }
+            if (lane == 0) {
+                eL[wv][0] = fs[3]; eL[wv][1] = fs[6]; eL[wv][2] = fs[7];
+                eL[wv][3] = fs[12]; eL[wv][4] = fs[15]; eL[wv][5] = fs[16];
+            }
+            __syncthreads();
+            if (lane == 0 && wv > 0) {
+                g[1] = eR[wv - 1][0]; g[5] = eR[wv - 1][1]; g[8] = eR[wv - 1][2];
+                g[10] = eR[wv - 1][3]; g[14] = eR[wv - 1][4]; g[17] = eR[wv - 1][5];
+            }
+            if (lane == 63 && wv < NW - 1) {
+                g[3] = eL[wv + 1][0]; g[6] = eL[wv + 1][1]; g[7] = eL[wv + 1][2];
+                g[12] = eL[wv + 1][3]; g[15] = eL[wv + 1][4]; g[16] = eL[wv + 1][5];
+            }
+            // C: stage-2 pull of row b = a - 2: directions 0,1,3 from row b, 2,5,6 from row
+            // b - 1, 4,7,8 from row b + 1 (this iteration's shifted values)
+            float f2[18];
+            float n2A = 0.0f, n2B = 0.0f;
+            uint32_t code2 = 0;
+#pragma unroll
+            for (int i = 0; i < 18; ++i) f2[i] = 0.0f;
+            if (k >= 4) {
+                const int b = wrap_mod(td.yb - 5 + k, c.ny);
+                if (MASK && c.masked)
+                    code2 = mask_code(c, ws, x, b);
+                else if (near_wall(c, b))
+                    code2 = rows_code(c, x, b);
+#pragma unroll
+                for (int m = 0; m < 2; ++m) {
+                    const int o = 9 * m;
+                    f2[o + 0] = gm1[6 * m + 0];
+                    f2[o + 1] = gm1[6 * m + 1];
+                    f2[o + 3] = gm1[6 * m + 2];
+                    f2[o + 2] = gm2[3 * m + 0];
+                    f2[o + 5] = gm2[3 * m + 1];
+                    f2[o + 6] = gm2[3 * m + 2];
+                    f2[o + 4] = g[o + 4];
+                    f2[o + 7] = g[o + 7];
+                    f2[o + 8] = g[o + 8];
+                }
+                if (code2) {
+#pragma unroll
+                    for (int i = 1; i < 9; ++i)
+                        if ((code2 >> opp[i]) & 1u) {
+                            f2[i] = uf[opp[i]];
+                            f2[9 + i] = uf[9 + opp[i]];
+                        }
+                }
+                if (!(code2 & 1u)) {
+                    n2A = sum9(f2);
+                    n2B = sum9(f2 + 9);
+                }
+            }
+            r2[0][s0][tid] = n2A;
+            r2[1][s0][tid] = n2B;
+            __syncthreads();
+            // D: stage-2 collision of row b - 1 (pulled one iteration ago), store f*(t + 1)
+            if (k >= 6 && in2 && !(q2code & 1u)) {
+                const int yc = wrap_mod(td.yb - 6 + k, c.ny);
+                float sAx, sAy, sBx, sBy;
+                ring_sums(r2[0][s2], r2[0][s1], r2[0][s0], r2[1][s2], r2[1][s1], r2[1][s0], tid,
+                          sAx, sAy, sBx, sBy);
+                float swx = 0.0f, swy = 0.0f;
+                if (q2code) wall_sum(q2code, swx, swy);
+                collide_store(c, q2, q2A, q2B, sAx, sAy, sBx, sBy, swx, swy,
+                              BufferOut{rd, Pb, (yc * c.pitch + x) * 4});
+            }
+#pragma unroll
+            for (int i = 0; i < 18; ++i) {
+                q[i] = p[i];
+                uf[i] = fs[i];
+                q2[i] = f2[i];
+            }
+            qA = nA;
+            qB = nB;
+            qcode = code;
+            q2A = n2A;
+            q2B = n2B;
+            q2code = code2;
+#pragma unroll
+            for (int m = 0; m < 2; ++m) {
+                const int o = 9 * m;
+                gm2[3 * m + 0] = gm1[6 * m + 3];
+                gm2[3 * m + 1] = gm1[6 * m + 4];
+                gm2[3 * m + 2] = gm1[6 * m + 5];
+                gm1[6 * m + 0] = g[o + 0];
+                gm1[6 * m + 1] = g[o + 1];
+                gm1[6 * m + 2] = g[o + 3];
+                gm1[6 * m + 3] = g[o + 2];
+                gm1[6 * m + 4] = g[o + 5];
+                gm1[6 * m + 5] = g[o + 6];
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------------------------
 // Two-kernel step: (1) densities of every node into the density field, (2) pull, neighbour
 // densities read back from the field, collision.  Same per-node arithmetic as the fused step.
 // One block per row; threads stride along x.
@@ -637,6 +877,17 @@ hipError_t launch_fused_bx(bool masked, const Chan* chans, const TileDesc* tiles
     return hipGetLastError();
 }
 
+template <int BX>
+hipError_t launch_fused2_bx(bool masked, const Chan* chans, const TileDesc* tiles, int ntiles,
+                            int grid, float* ws, int src, hipStream_t s) {
+    const int g = grid > 0 ? min(grid, ntiles) : ntiles;
+    if (masked)
+        hipLaunchKernelGGL((k_step_fused2<BX, true>), dim3(g), dim3(BX), 0, s, chans, tiles, ntiles, ws, src);
+    else
+        hipLaunchKernelGGL((k_step_fused2<BX, false>), dim3(g), dim3(BX), 0, s, chans, tiles, ntiles, ws, src);
+    return hipGetLastError();
+}
+
 // Solid-neighbourhood codes of masked channels from the staged uint8 mask (ny*nx bytes after
 // the two FP64 fields in population buffer 1).  Row-walled channels are skipped.
 __global__ void __launch_bounds__(kRowThreads)
@@ -678,6 +929,17 @@ hipError_t launch_step_fused(int bx, bool masked, const Chan* chans, const TileD
         case 128: return launch_fused_bx<128>(masked, chans, tiles, ntiles, grid, ws, src, s);
         case 256: return launch_fused_bx<256>(masked, chans, tiles, ntiles, grid, ws, src, s);
         case 512: return launch_fused_bx<512>(masked, chans, tiles, ntiles, grid, ws, src, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_step_fused2(int bx, bool masked, const Chan* chans, const TileDesc* tiles,
+                              int ntiles, int grid, float* ws, int src, hipStream_t s) {
+    switch (bx) {
+        case 64: return launch_fused2_bx<64>(masked, chans, tiles, ntiles, grid, ws, src, s);
+        case 128: return launch_fused2_bx<128>(masked, chans, tiles, ntiles, grid, ws, src, s);
+        case 256: return launch_fused2_bx<256>(masked, chans, tiles, ntiles, grid, ws, src, s);
+        case 512: return launch_fused2_bx<512>(masked, chans, tiles, ntiles, grid, ws, src, s);
         default: return hipErrorInvalidValue;
     }
 }

@@ -94,7 +94,8 @@ struct Layout {
     int nrows = 0, max_tiles = 0;
 };
 
-int max_tiles_of(const scf_geometry& g) { return ((g.nx + 63) / 64) * g.ny; }   // bx = 64, cy = 1
+// Most tiles one list can hold: 60-column strips (bx = 64 with two steps per pass), cy = 1.
+int max_tiles_of(const scf_geometry& g) { return ((g.nx + 59) / 60) * g.ny; }
 
 Layout plan(int nchan, const scf_geometry* g, int max_samples) {
     Layout L;
@@ -103,7 +104,8 @@ Layout plan(int nchan, const scf_geometry* g, int max_samples) {
     for (int c = 0; c < nchan; ++c) { L.nrows += g[c].ny; L.max_tiles += max_tiles_of(g[c]); }
     L.rows = off; off = align_up(off + sizeof(scf::RowRef) * L.nrows, 256);
     L.max_tiles += 8;   // padding of the XCD-contiguous order
-    L.tiles = off; off = align_up(off + sizeof(scf::TileDesc) * L.max_tiles, 256);
+    // two lists: single-step tiles, then the two-step tiles
+    L.tiles = off; off = align_up(off + sizeof(scf::TileDesc) * 2 * (size_t)L.max_tiles, 256);
     L.parts = off; off = align_up(off + sizeof(scf::RowPartial) * L.nrows, 256);
     L.now = off; off = align_up(off + sizeof(scf::ObsRec) * nchan, 256);
     L.ring = off; off = align_up(off + sizeof(scf::ObsRec) * (size_t)nchan * max_samples, 256);
@@ -160,8 +162,8 @@ struct Engine {
     int cur = 0;
     int64_t t = 0;
     int variant = SCF_VARIANT_FUSED;
-    int bx = 256, cy = 64, order = SCF_ORDER_STRIPS, graph_steps = 64, grid = 0;
-    int ntiles = 0;
+    int bx = 256, cy = 64, order = SCF_ORDER_STRIPS, graph_steps = 64, grid = 0, fuse = 1;
+    int ntiles = 0, ntiles2 = 0;
     hipGraphExec_t g_steps[2] = {nullptr, nullptr};
     hipGraphExec_t g_sample[2] = {nullptr, nullptr};
     int sample_every = 0, max_samples = 1;
@@ -171,6 +173,7 @@ struct Engine {
     scf::Chan* d_chans() const { return reinterpret_cast<scf::Chan*>(ws + lay.chans); }
     scf::RowRef* d_rows() const { return reinterpret_cast<scf::RowRef*>(ws + lay.rows); }
     scf::TileDesc* d_tiles() const { return reinterpret_cast<scf::TileDesc*>(ws + lay.tiles); }
+    scf::TileDesc* d_tiles2() const { return d_tiles() + lay.max_tiles; }
     scf::RowPartial* d_parts() const { return reinterpret_cast<scf::RowPartial*>(ws + lay.parts); }
     scf::ObsRec* d_now() const { return reinterpret_cast<scf::ObsRec*>(ws + lay.now); }
     scf::ObsRec* d_ring() const { return reinterpret_cast<scf::ObsRec*>(ws + lay.ring); }
@@ -195,6 +198,7 @@ struct Engine {
     // round-robin to the 8 XCDs; with SCF_ORDER_XCD the list is permuted so that each XCD gets
     // a contiguous eighth of the base order (empty tiles pad the last round).
     std::vector<scf::TileDesc> make_tiles(int bxv, int cyv, int ord) const {
+        // bxv is the strip width: bx for single steps, bx - 4 for two steps per pass
         const bool bands = (ord & SCF_ORDER_BANDS) != 0;
         std::vector<scf::TileDesc> tl;
         for (int c = 0; c < nchan; ++c) {
@@ -233,21 +237,39 @@ struct Engine {
 
     int upload_tiles(int bxv, int cyv, int ord) {
         std::vector<scf::TileDesc> tl = make_tiles(bxv, cyv, ord);
-        if ((int)tl.size() > lay.max_tiles) return fail(SCF_EINVAL, "tile list exceeds its reserved space");
+        std::vector<scf::TileDesc> tl2 = make_tiles(bxv - 4, cyv, ord);
+        if ((int)tl.size() > lay.max_tiles || (int)tl2.size() > lay.max_tiles)
+            return fail(SCF_EINVAL, "tile list exceeds its reserved space");
         HIP_TRY(hipMemcpyAsync(d_tiles(), tl.data(), sizeof(scf::TileDesc) * tl.size(),
+                               hipMemcpyHostToDevice, stream));
+        HIP_TRY(hipMemcpyAsync(d_tiles2(), tl2.data(), sizeof(scf::TileDesc) * tl2.size(),
                                hipMemcpyHostToDevice, stream));
         HIP_TRY(hipStreamSynchronize(stream));
         ntiles = (int)tl.size();
+        ntiles2 = (int)tl2.size();
         bx = bxv;
         cy = cyv;
         order = ord;
         return SCF_OK;
     }
 
-    hipError_t launch_step(hipStream_t s, int src) const {
+    // Steps one launch advances from parity src (two with fuse = 2 when n >= 2 are left).
+    int steps_of_launch(int64_t n) const {
+        return (variant == SCF_VARIANT_FUSED && fuse == 2 && n >= 2) ? 2 : 1;
+    }
+
+    // One launch of `k` (1 or 2) steps reading buffer src and writing src ^ 1.
+    hipError_t launch_steps(hipStream_t s, int src, int k) const {
+        if (k == 2)
+            return scf::launch_step_fused2(bx, any_masked, d_chans(), d_tiles2(), ntiles2, grid, base(), src, s);
         if (variant == SCF_VARIANT_TWO_KERNEL)
             return scf::launch_step_two_kernel(d_chans(), d_rows(), lay.nrows, base(), src, s);
         return scf::launch_step_fused(bx, any_masked, d_chans(), d_tiles(), ntiles, grid, base(), src, s);
+    }
+
+    // Launches that advance n steps (each flips the resident buffer once).
+    int64_t launches_for(int64_t n) const {
+        return (variant == SCF_VARIANT_FUSED && fuse == 2) ? n / 2 + (n & 1) : n;
     }
 
     hipError_t launch_obs(hipStream_t s, int record) const {
@@ -262,9 +284,11 @@ struct Engine {
         HIP_TRY(hipStreamBeginCapture(cap, hipStreamCaptureModeRelaxed));
         hipError_t err = hipSuccess;
         int src = p;
-        for (int i = 0; i < n && err == hipSuccess; ++i) {
-            err = launch_step(cap, src);
+        for (int64_t left = n; left > 0 && err == hipSuccess;) {
+            const int k = steps_of_launch(left);
+            err = launch_steps(cap, src, k);
             src ^= 1;
+            left -= k;
         }
         if (err == hipSuccess && observe)
             err = scf::launch_observe(d_chans(), d_rows(), lay.nrows, nchan, base(), src, d_parts(),
@@ -290,14 +314,15 @@ struct Engine {
                     if (rc) return rc;
                 }
                 HIP_TRY(hipGraphLaunch(g_steps[cur], stream));
-                cur ^= (graph_steps & 1);
+                cur ^= (int)(launches_for(graph_steps) & 1);
                 t += graph_steps;
                 n -= graph_steps;
             } else {
-                HIP_TRY(launch_step(stream, cur));
+                const int k = steps_of_launch(n);
+                HIP_TRY(launch_steps(stream, cur, k));
                 cur ^= 1;
-                t += 1;
-                n -= 1;
+                t += k;
+                n -= k;
             }
         }
         return SCF_OK;
@@ -321,7 +346,7 @@ struct Engine {
                     if (rc) return rc;
                 }
                 HIP_TRY(hipGraphLaunch(g_sample[cur], stream));
-                cur ^= (S & 1);
+                cur ^= (int)(launches_for(S) & 1);
                 t += S;
                 n -= S;
                 recorded += 1;
@@ -412,9 +437,11 @@ struct Engine {
         if (tl->cy < 1) return fail(SCF_EINVAL, "cy must be >= 1");
         if (tl->order < 0 || tl->order > (SCF_ORDER_BANDS | SCF_ORDER_XCD)) return fail(SCF_EINVAL, "unknown order");
         if (tl->graph_steps < 0) return fail(SCF_EINVAL, "graph_steps must be >= 0");
+        if (tl->fuse != 1 && tl->fuse != 2) return fail(SCF_EINVAL, "fuse must be 1 or 2");
         HIP_TRY(hipStreamSynchronize(stream));
         drop_graphs();
         graph_steps = tl->graph_steps;
+        fuse = tl->fuse;
         return upload_tiles(tl->bx, tl->cy, tl->order);
     }
 
@@ -423,6 +450,7 @@ struct Engine {
         tl->cy = cy;
         tl->order = order;
         tl->graph_steps = graph_steps;
+        tl->fuse = fuse;
     }
 
     // Time each candidate by repeated steps that all read the resident buffer and write the
@@ -437,8 +465,8 @@ struct Engine {
         hipEvent_t e0, e1;
         HIP_TRY(hipEventCreate(&e0));
         HIP_TRY(hipEventCreate(&e1));
-        float best = std::numeric_limits<float>::max();
-        int bbx = bx, bcy = cy, bord = order;
+        float best = std::numeric_limits<float>::max();   // ms per time step
+        int bbx = bx, bcy = cy, bord = order, bfuse = fuse;
         const int saved_variant = variant;
         variant = SCF_VARIANT_FUSED;
         int rc = SCF_OK;
@@ -448,14 +476,18 @@ struct Engine {
                     if (cyv != (1 << 30) && cyv >= maxny) continue;
                     rc = upload_tiles(bxv, cyv, ord);
                     if (rc) break;
-                    for (int i = 0; i < 2; ++i) (void)launch_step(stream, cur);
-                    (void)hipEventRecord(e0, stream);
-                    for (int i = 0; i < trial; ++i) (void)launch_step(stream, cur);
-                    (void)hipEventRecord(e1, stream);
-                    if (hipEventSynchronize(e1) != hipSuccess) { rc = fail(SCF_EDEVICE, "autotune timing failed"); break; }
-                    float ms = 0.0f;
-                    (void)hipEventElapsedTime(&ms, e0, e1);
-                    if (ms < best) { best = ms; bbx = bxv; bcy = cyv; bord = ord; }
+                    for (int k = 1; k <= 2; ++k) {
+                        for (int i = 0; i < 2; ++i) (void)launch_steps(stream, cur, k);
+                        (void)hipEventRecord(e0, stream);
+                        for (int i = 0; i < trial; ++i) (void)launch_steps(stream, cur, k);
+                        (void)hipEventRecord(e1, stream);
+                        if (hipEventSynchronize(e1) != hipSuccess) { rc = fail(SCF_EDEVICE, "autotune timing failed"); break; }
+                        float ms = 0.0f;
+                        (void)hipEventElapsedTime(&ms, e0, e1);
+                        ms /= (float)k;
+                        if (ms < best) { best = ms; bbx = bxv; bcy = cyv; bord = ord; bfuse = k; }
+                    }
+                    if (rc) break;
                 }
                 if (rc) break;
             }
@@ -464,6 +496,7 @@ struct Engine {
         variant = saved_variant;
         if (rc) return rc;
         drop_graphs();
+        fuse = bfuse;
         rc = upload_tiles(bbx, bcy, bord);
         if (rc) return rc;
         if (chosen) get_tile(chosen);

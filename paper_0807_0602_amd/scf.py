@@ -118,8 +118,8 @@ class Channel:
     def set_variant(self, variant: int) -> None:
         L.check(L.scf_set_variant(self._h, int(variant)))
 
-    def set_tile(self, bx: int, cy: int, graph_steps: int = 64, order: int = 0) -> None:
-        t = L.scf_tile(int(bx), int(cy), int(order), int(graph_steps))
+    def set_tile(self, bx: int, cy: int, graph_steps: int = 64, order: int = 0, fuse: int = 1) -> None:
+        t = L.scf_tile(int(bx), int(cy), int(order), int(graph_steps), int(fuse))
         L.check(L.scf_set_tile(self._h, C.byref(t)))
 
     def tile(self) -> dict:
@@ -194,8 +194,8 @@ class Batch:
         L.check(L.scf_batch_get_density(self._h, int(c), _dptr(a), _dptr(b)))
         return a, b
 
-    def set_tile(self, bx: int, cy: int, graph_steps: int = 64, order: int = 0) -> None:
-        t = L.scf_tile(int(bx), int(cy), int(order), int(graph_steps))
+    def set_tile(self, bx: int, cy: int, graph_steps: int = 64, order: int = 0, fuse: int = 1) -> None:
+        t = L.scf_tile(int(bx), int(cy), int(order), int(graph_steps), int(fuse))
         L.check(L.scf_batch_set_tile(self._h, C.byref(t)))
 
     def tile(self) -> dict:
