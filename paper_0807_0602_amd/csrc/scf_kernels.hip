@@ -379,7 +379,9 @@ k_step_fused(const Chan* __restrict__ chans, const TileDesc* __restrict__ tiles,
 // pulls row yb-3+k, stage 1 collides row yb-4+k, stage 2 pulls row yb-5+k and collides and
 // stores row yb-6+k.  Three barriers per row: after the stage-1 densities, after the edge
 // values, after the stage-2 densities.  Each node is computed with exactly the arithmetic of
-// the single step, so two stages equal two single steps bit for bit.
+// the single step, so two stages equal two single steps bit for bit.  The kernel is held to
+// three waves per SIMD (at most 168 VGPRs, no spills): faster than two waves with the
+// registers it would otherwise take, and than four with spills.
 // ---------------------------------------------------------------------------------------------
 struct RegOut {
     float* r;
@@ -414,7 +416,7 @@ __device__ __forceinline__ void ring_sums(const float* Am, const float* Ao, cons
 }
 
 template <int BX, bool MASK>
-__global__ void __launch_bounds__(BX)
+__global__ void __launch_bounds__(BX) __attribute__((amdgpu_waves_per_eu(3, 3)))
 k_step_fused2(const Chan* __restrict__ chans, const TileDesc* __restrict__ tiles, int ntiles,
               float* __restrict__ ws, int src) {
     constexpr int NW = BX / 64;
