@@ -60,9 +60,23 @@ def measured_traffic(cells: int, schedule: dict):
     if t.get("kernel_sha256_16") != kernel_hash() or t.get("cells") != cells:
         return None
     for e in t.get("schedules", []):
-        if all(e["schedule"].get(k) == schedule.get(k) for k in ("bx", "cy", "order")):
+        if all(e["schedule"].get(k, 1 if k == "fuse" else None) == schedule.get(k, 1 if k == "fuse" else None)
+               for k in ("bx", "cy", "order", "fuse")):
             return e["bytes_per_launch"]
     return None
+
+
+def kernel_name(fuse: int) -> str:
+    return "k_step_fused2" if fuse == 2 else "k_step_fused"
+
+
+def parse_tile(vals):
+    """--tile BX CY ORDER [FUSE] -> (bx, cy, order, fuse)."""
+    if vals is None:
+        return None
+    if len(vals) not in (3, 4):
+        raise SystemExit("--tile takes BX CY ORDER [FUSE]")
+    return (vals[0], vals[1], vals[2], vals[3] if len(vals) == 4 else 1)
 
 
 def _counter_mean(path: str, kernel: str, counter: str) -> float:
@@ -79,12 +93,13 @@ def summarize_counters(args) -> int:
     calibration copy into TRAFFIC_FILE (one entry per schedule).  Each counter is scaled by
     (bytes the copy kernel moves) / (what the counter reads for it)."""
     fetch, write, fetch_copy, write_copy = args.summarize_counters
-    bx, cy, order = args.tile
+    bx, cy, order, fuse = args.tile
+    kname = kernel_name(fuse) + "<"    # template instantiations only (not the other kernel)
     copy_kib = (1 << 30) / 1024.0
     f_scale = copy_kib / _counter_mean(fetch_copy, "copyBuffer", "FETCH_SIZE")
     w_scale = copy_kib / _counter_mean(write_copy, "copyBuffer", "WRITE_SIZE")
-    rd = _counter_mean(fetch, "k_step_fused", "FETCH_SIZE") * f_scale * 1024.0
-    wr = _counter_mean(write, "k_step_fused", "WRITE_SIZE") * w_scale * 1024.0
+    rd = _counter_mean(fetch, kname, "FETCH_SIZE") * f_scale * 1024.0
+    wr = _counter_mean(write, kname, "WRITE_SIZE") * w_scale * 1024.0
     from paper_0807_0602_amd import inputs
     case = inputs.capillary_roofline(seed=1)
     cells = case.geom.nx * case.geom.ny
@@ -94,9 +109,9 @@ def summarize_counters(args) -> int:
     except (OSError, ValueError):
         t = {}
     if t.get("kernel_sha256_16") != kernel_hash() or t.get("cells") != cells:
-        t = {"kernel": "k_step_fused", "workload": case.name, "cells": cells,
+        t = {"kernel": "k_step_fused / k_step_fused2", "workload": case.name, "cells": cells,
              "kernel_sha256_16": kernel_hash(), "schedules": []}
-    sched = {"bx": bx, "cy": cy, "order": order}
+    sched = {"bx": bx, "cy": cy, "order": order, "fuse": fuse}
     t["schedules"] = [e for e in t["schedules"] if e["schedule"] != sched]
     t["schedules"].append({"schedule": sched, "read_bytes_per_launch": round(rd),
                            "write_bytes_per_launch": round(wr), "bytes_per_launch": round(rd + wr),
@@ -151,11 +166,12 @@ def sweep(args) -> int:
     stream = torch.cuda.current_stream()
     b = Batch(cases, sample_every=every, max_samples=steps // every + 1, stream=stream)
     if args.tile:
-        b.set_tile(args.tile[0], args.tile[1], every, args.tile[2])
+        bx, cy, order, fuse = args.tile
+        b.set_tile(bx, cy, every, order, fuse)
     else:
         b.autotune(5)
         t = b.tile()
-        b.set_tile(t["bx"], t["cy"], every, t["order"])
+        b.set_tile(t["bx"], t["cy"], every, t["order"], t["fuse"])
     tile = b.tile()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
@@ -169,7 +185,7 @@ def sweep(args) -> int:
     recs, ns = b.observe(allow_unstable=True)
     unstable = sum(1 for r in recs if any(x["flags"] & 2 for x in r))
     step_s = e0.elapsed_time(e1) / 1e3 / steps
-    achieved = 144 * cells / step_s / 1e9
+    achieved = 144 * cells / step_s / 1e9    # 144 B per node update (single-step equivalent)
     line = {
         "metric": "calibration-sweep points/hour, batched LBM (one point = one channel trajectory)",
         "value": round(len(cases) * 3600.0 / wall, 1), "unit": "points/h", "n_gpus": 1,
@@ -183,8 +199,8 @@ def sweep(args) -> int:
                    "unstable_channels": unstable},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": "k_step_fused (all channels per launch) + observation every 100 steps",
-                     "bytes_per_node_update": 144},
+                     "kernel": kernel_name(tile["fuse"]) + " (all channels per launch) + observation every 100 steps",
+                     "bytes_per_node_update": 144, "steps_per_launch": tile["fuse"]},
     }
     print(json.dumps(line), flush=True)
     return 0
@@ -243,13 +259,15 @@ def main() -> int:
     ap.add_argument("--variant", choices=["fused", "two_kernel"], default="fused")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true")
-    ap.add_argument("--tile", type=int, nargs=3, default=None, metavar=("BX", "CY", "ORDER"))
+    ap.add_argument("--tile", type=int, nargs="+", default=None, metavar="N",
+                    help="BX CY ORDER [FUSE]: fixed schedule instead of the autotuner")
     ap.add_argument("--workload", choices=["roofline", "sweep", "surrogate"], default="roofline")
     ap.add_argument("--weights", default=os.path.join(ROOT, "paper_0807_0602_amd", "surrogate_weights_5in.npz"))
     ap.add_argument("--summarize-counters", nargs=4, default=None,
                     metavar=("FETCH_CSV", "WRITE_CSV", "FETCH_COPY_CSV", "WRITE_COPY_CSV"),
                     help="write the traffic summary for the schedule given by --tile and exit")
     args = ap.parse_args()
+    args.tile = parse_tile(args.tile)
     if args.summarize_counters:
         if not args.tile:
             raise SystemExit("--summarize-counters needs --tile BX CY ORDER")
@@ -280,11 +298,13 @@ def main() -> int:
     ch = Channel.from_case(case, stream=stream)
     variant = L.SCF_VARIANT_FUSED if args.variant == "fused" else L.SCF_VARIANT_TWO_KERNEL
     if args.tile:
-        ch.set_tile(args.tile[0], args.tile[1], 64, args.tile[2])
+        bx, cy, order, fuse = args.tile
+        ch.set_tile(bx, cy, 64, order, fuse)
     else:
         ch.autotune(20)
     tile = ch.tile()
     ch.set_variant(variant)
+    fuse = tile["fuse"] if args.variant == "fused" else 1
     ch.step(args.warmup)
     torch.cuda.synchronize()
 
@@ -301,9 +321,11 @@ def main() -> int:
     obs = ch.observe(allow_unstable=True)
 
     mlups = cells * args.steps / wall / 1e6
-    step_s = ev_ms / 1e3 / args.steps          # one kernel launch per fused step
+    step_s = ev_ms / 1e3 / args.steps
+    launch_s = step_s * fuse                   # one launch advances `fuse` steps
     bpl = BYTES_PER_LUP[args.variant]
-    achieved = bpl * cells / step_s / 1e9
+    # algorithmic bytes per launch: bpl per node update x the node updates of one launch
+    achieved = bpl * cells * fuse / launch_s / 1e9
     traffic = measured_traffic(cells, tile) if args.variant == "fused" else None
     line = {
         "metric": METRIC, "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1,
@@ -315,8 +337,10 @@ def main() -> int:
                    "variant": args.variant, "schedule": tile, "nodes": cells},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                     "kernel": "k_step_fused" if args.variant == "fused" else "k_density+k_collide",
-                     "bytes_per_node_update": bpl, "event_ms_per_step": round(step_s * 1e3, 5)},
+                     "kernel": kernel_name(fuse) if args.variant == "fused" else "k_density+k_collide",
+                     "bytes_per_node_update": bpl, "steps_per_launch": fuse,
+                     "event_ms_per_launch": round(launch_s * 1e3, 5),
+                     "traffic_gbs": round(traffic / launch_s / 1e9, 1) if traffic else None},
         "health": {"flags": obs["flags"], "z": obs["z"], "mass": list(obs["mass"])},
     }
     if not args.no_cpu_baseline:

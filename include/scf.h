@@ -154,10 +154,10 @@ int scf_set_variant(scf_ctx* ctx, int32_t variant);
 int scf_set_tile(scf_ctx* ctx, const scf_tile* tile);
 int scf_get_tile(const scf_ctx* ctx, scf_tile* tile);
 
-/* Time candidate schedules (bx, cy, order, fuse) for `trial_steps` launches each and keep the
- * fastest per time step.  Every trial launch reads the resident buffer and writes the idle one,
- * so the state is unchanged.  The graph length is kept.  Writes the chosen schedule to *chosen
- * if non-NULL. */
+/* Time candidate schedules (bx, cy, order, fuse) for `trial_steps` launches each, time the
+ * best eight again with 4 x trial_steps launches, and keep the fastest per time step.  Every
+ * trial launch reads the resident buffer and writes the idle one, so the state is unchanged.
+ * The graph length is kept.  Writes the chosen schedule to *chosen if non-NULL. */
 int scf_autotune(scf_ctx* ctx, int32_t trial_steps, scf_tile* chosen);
 
 /* Elapsed time step count of the context. */

@@ -465,39 +465,48 @@ struct Engine {
         hipEvent_t e0, e1;
         HIP_TRY(hipEventCreate(&e0));
         HIP_TRY(hipEventCreate(&e1));
-        float best = std::numeric_limits<float>::max();   // ms per time step
-        int bbx = bx, bcy = cy, bord = order, bfuse = fuse;
         const int saved_variant = variant;
         variant = SCF_VARIANT_FUSED;
-        int rc = SCF_OK;
-        for (int ord = 0; ord < 4 && !rc; ++ord)
-            for (int bxv : bxs) {
+        struct Cand { int bx, cy, ord, fuse; float ms; };   // ms per time step
+        std::vector<Cand> cands;
+        for (int ord = 0; ord < 4; ++ord)
+            for (int bxv : bxs)
                 for (int cyv : cys) {
                     if (cyv != (1 << 30) && cyv >= maxny) continue;
-                    rc = upload_tiles(bxv, cyv, ord);
-                    if (rc) break;
-                    for (int k = 1; k <= 2; ++k) {
-                        for (int i = 0; i < 2; ++i) (void)launch_steps(stream, cur, k);
-                        (void)hipEventRecord(e0, stream);
-                        for (int i = 0; i < trial; ++i) (void)launch_steps(stream, cur, k);
-                        (void)hipEventRecord(e1, stream);
-                        if (hipEventSynchronize(e1) != hipSuccess) { rc = fail(SCF_EDEVICE, "autotune timing failed"); break; }
-                        float ms = 0.0f;
-                        (void)hipEventElapsedTime(&ms, e0, e1);
-                        ms /= (float)k;
-                        if (ms < best) { best = ms; bbx = bxv; bcy = cyv; bord = ord; bfuse = k; }
-                    }
-                    if (rc) break;
+                    for (int k = 1; k <= 2; ++k) cands.push_back({bxv, cyv, ord, k, 0.0f});
                 }
-                if (rc) break;
-            }
+        // time every candidate with `trial` launches, then the best eight again with four
+        // times as many, and keep the fastest of the second round
+        auto time_cand = [&](Cand& cd, int launches) -> int {
+            int rc = upload_tiles(cd.bx, cd.cy, cd.ord);
+            if (rc) return rc;
+            for (int i = 0; i < 2; ++i) (void)launch_steps(stream, cur, cd.fuse);
+            (void)hipEventRecord(e0, stream);
+            for (int i = 0; i < launches; ++i) (void)launch_steps(stream, cur, cd.fuse);
+            (void)hipEventRecord(e1, stream);
+            if (hipEventSynchronize(e1) != hipSuccess) return fail(SCF_EDEVICE, "autotune timing failed");
+            float ms = 0.0f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            cd.ms = ms / (float)(launches * cd.fuse);
+            return SCF_OK;
+        };
+        int rc = SCF_OK;
+        for (Cand& cd : cands)
+            if ((rc = time_cand(cd, trial))) break;
+        if (!rc) {
+            std::sort(cands.begin(), cands.end(), [](const Cand& a, const Cand& b) { return a.ms < b.ms; });
+            cands.resize(std::min<size_t>(cands.size(), 8));
+            for (Cand& cd : cands)
+                if ((rc = time_cand(cd, 4 * trial))) break;
+            std::sort(cands.begin(), cands.end(), [](const Cand& a, const Cand& b) { return a.ms < b.ms; });
+        }
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
         variant = saved_variant;
         if (rc) return rc;
         drop_graphs();
-        fuse = bfuse;
-        rc = upload_tiles(bbx, bcy, bord);
+        fuse = cands[0].fuse;
+        rc = upload_tiles(cands[0].bx, cands[0].cy, cands[0].ord);
         if (rc) return rc;
         if (chosen) get_tile(chosen);
         return SCF_OK;

@@ -77,7 +77,8 @@ def test_bench_counter_summary(tmp_path, monkeypatch):
 
     class A:
         summarize_counters = files
-        tile = [256, 16, 1]
+        tile = bench.parse_tile([256, 16, 1])
+    assert A.tile == (256, 16, 1, 1)
     assert bench.summarize_counters(A) == 0
     t = json.load(open(tmp_path / "traffic.json"))
     e = t["schedules"][0]
@@ -85,4 +86,21 @@ def test_bench_counter_summary(tmp_path, monkeypatch):
     assert e["read_bytes_per_launch"] == 600000 * 2 * 1024 and e["write_bytes_per_launch"] == 1179000 * 1024
     cells = 16384 * 1024
     assert bench.measured_traffic(cells, {"bx": 256, "cy": 16, "order": 1}) == e["bytes_per_launch"]
+    assert bench.measured_traffic(cells, {"bx": 256, "cy": 16, "order": 1, "fuse": 1}) == e["bytes_per_launch"]
+    assert bench.measured_traffic(cells, {"bx": 256, "cy": 16, "order": 1, "fuse": 2}) is None
     assert bench.measured_traffic(cells, {"bx": 256, "cy": 8, "order": 1}) is None
+    # a two-step schedule reads the counters of k_step_fused2 only
+    files2 = []
+    for name, kern, ctr, vals in [("f2", "k_step_fused2<256, false>", "FETCH_SIZE", [900000]),
+                                  ("w2", "k_step_fused2<256, false>", "WRITE_SIZE", [1179000])]:
+        p = str(tmp_path / f"{name}.csv")
+        _counter_csv(p, kern, ctr, vals)
+        files2.append(p)
+
+    class B:
+        summarize_counters = files2 + files[2:]
+        tile = bench.parse_tile([256, 16, 1, 2])
+    assert bench.summarize_counters(B) == 0
+    t = json.load(open(tmp_path / "traffic.json"))
+    assert len(t["schedules"]) == 2
+    assert bench.measured_traffic(cells, {"bx": 256, "cy": 16, "order": 1, "fuse": 2}) == (900000 * 2 + 1179000) * 1024
