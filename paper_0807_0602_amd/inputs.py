@@ -274,6 +274,20 @@ def plug_fields(geom: Geometry, xa: int, xb: int, rho_liq: float = 2.0,
     return np.ascontiguousarray(rhoA), np.ascontiguousarray(rhoB)
 
 
+def sessile_fields(geom: Geometry, xc: float, R: float, rho_liq: float = 2.0,
+                   rho_min: float = 0.06) -> Tuple[np.ndarray, np.ndarray]:
+    """A half-disc of A of radius R centred at (xc, 0.5) on the bottom wall plane (between the
+    solid row 0 and the first fluid row), B elsewhere; solid nodes zero."""
+    Y, X = np.meshgrid(np.arange(geom.ny), np.arange(geom.nx), indexing="ij")
+    inside = (X - xc) ** 2 + (Y - 0.5) ** 2 < R * R
+    rhoA = np.where(inside, rho_liq, rho_min).astype(np.float64)
+    rhoB = np.where(inside, rho_min, rho_liq).astype(np.float64)
+    solid = geom.solid_mask()
+    rhoA[solid] = 0.0
+    rhoB[solid] = 0.0
+    return np.ascontiguousarray(rhoA), np.ascontiguousarray(rhoB)
+
+
 def with_params(case: Case, **kw) -> Case:
     """Copy of a case with some Params fields replaced."""
     return replace(case, params=replace(case.params, **kw))

@@ -143,7 +143,9 @@ class Batch:
     """Many independent channels advanced together (scf_batch_*)."""
 
     def __init__(self, cases: Sequence[Case], sample_every: int, max_samples: int, device="cuda:0",
-                 stream: Optional[torch.cuda.Stream] = None):
+                 stream: Optional[torch.cuda.Stream] = None,
+                 fields: Optional[Sequence[Tuple[np.ndarray, np.ndarray]]] = None):
+        """`fields`: optional initial (rhoA, rhoB) per channel in place of each case's own."""
         self.cases = list(cases)
         n = len(self.cases)
         self._m = [_mask(c.geom) for c in self.cases]
@@ -155,7 +157,13 @@ class Batch:
         if nbytes == 0:
             raise L.ScfError(L.SCF_EINVAL, "invalid batch geometry")
         self.ws = _workspace(nbytes, device)
-        fields = [c.fields() for c in self.cases]
+        if fields is None:
+            fields = [c.fields() for c in self.cases]
+        if len(fields) != n:
+            raise ValueError("one (rhoA, rhoB) pair per case")
+        for (a, b), c in zip(fields, self.cases):
+            if np.shape(a) != (c.geom.ny, c.geom.nx) or np.shape(b) != (c.geom.ny, c.geom.nx):
+                raise ValueError("density fields must have shape (ny, nx)")
         self._keep = [(np.ascontiguousarray(a), np.ascontiguousarray(b)) for a, b in fields]
         pa = (C.POINTER(C.c_double) * n)(*[_dptr(a) for a, _ in self._keep])
         pb = (C.POINTER(C.c_double) * n)(*[_dptr(b) for _, b in self._keep])

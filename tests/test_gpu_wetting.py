@@ -1,0 +1,106 @@
+"""Wettability on the GPU: the a-posteriori contact angle (Sec. 2) by two estimators, and the
+paper's two routes to the same angle (Sec. 3, the comparison of its front-displacement figure):
+an attractive liquid-wall coupling alone, or a repulsive gas-wall coupling alone.
+
+Bars: Laplace's law holds on free droplets (spread of Delta p R <= 3 %, zero intercept); the
+static-meniscus pressure jump equals the FP64 oracle's on the same plug (1 %); the meniscus and
+sessile-droplet estimators agree to 0.05 in cos(theta), neutral walls give 90 degrees, swapping
+the components' couplings flips the sign; and the two routes, matched to the same static angle,
+fill a capillary alike: late front speeds within 10 %, fronts within 6 % of the distance filled.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_0807_0602_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(m):
+    print(m, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def W():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_0807_0602_amd import wetting
+    return wetting
+
+
+@pytest.fixture(scope="module")
+def gamma(W):
+    lt = W.laplace_tension((1.0, 1.0))
+    _say(f"gamma = {lt['gamma']:.5f} intercept = {lt['intercept']:.2e}")
+    return lt
+
+
+def test_laplace_law(gamma):
+    dpR = np.asarray(gamma["dp"]) * np.asarray(gamma["R"])
+    assert dpR.std() / dpR.mean() <= 0.03
+    assert abs(gamma["intercept"]) <= 0.05 * gamma["dp"][-1]
+    assert 0.16 < gamma["gamma"] < 0.21
+
+
+def test_meniscus_matches_oracle(W, gamma):
+    """The plug's steady state, GPU (FP32) against the FP64 oracle on the same input."""
+    H, L, steps = 22, 160, 20000
+    geom = inputs.Geometry(L, H + 2, 0, L)
+    prm = inputs.Params(G=0.9, gw=(-0.2, 0.2), tau=(1.0, 1.0))
+    _say(f"case: plug {L}x{H + 2}, {steps} steps, GPU and oracle")
+    men = W.meniscus_cos([W.WallCase((-0.2, 0.2))], gamma["gamma"], H=H, L=L, steps=steps)[0]
+    a, b = inputs.plug_fields(geom, L // 4, 3 * L // 4)
+    oracle.set_threads(16)
+    o = oracle.Oracle(L, H + 2, 0, L, prm.G, prm.gw, prm.tau).init(a, b).step(steps)
+    nA, nB = o.density()
+    p = W.eos_pressure(nA, nB, prm.G)
+    rows, q = slice(1 + H // 4, 1 + 3 * H // 4), L // 16
+    dp = np.concatenate([p[rows, :q], p[rows, L - q:]], axis=1).mean() - p[rows, L // 2 - q:L // 2 + q].mean()
+    _say(f"  dp GPU {men['dp']:.6e}  oracle {dp:.6e}  cos {men['cos']:.4f}")
+    assert abs(men["dp"] - dp) <= 0.01 * abs(dp)
+    assert men["cos"] > 0.3
+
+
+def test_contact_angle_map(W, gamma):
+    gws = [(-0.3, 0.0), (-0.2, 0.2), (0.0, 0.0), (0.0, 0.3), (0.2, -0.2)]
+    _say("case: contact-angle map, 5 couplings x 2 estimators")
+    m = W.contact_angle_map(gws, [(1.0, 1.0)], gammas={(1.0, 1.0): gamma["gamma"]})
+    cm, cs = m["cos_meniscus"][0], m["cos_sessile"][0]
+    for g, a, b in zip(gws, cm, cs):
+        _say(f"  gw {g}: cos meniscus {a:.4f} sessile {b:.4f}")
+    assert np.all(np.abs(cm - cs) <= 0.05)
+    assert abs(cm[2]) <= 0.01 and abs(cs[2]) <= 0.03          # neutral walls: 90 degrees
+    assert abs(cm[1] + cm[4]) <= 0.01                          # swapped couplings: opposite angle
+    assert cm[1] > cm[0] > 0 and cm[3] > 0 and cm[4] < 0
+    assert not np.any(m["flags"] & 2)
+
+
+@pytest.mark.parametrize("tau", [(1.0, 1.0), (1.25, 1.0)])
+def test_two_wetting_routes_fill_alike(W, tau):
+    from paper_0807_0602_amd.scf import Batch
+    eq = W.equivalent_couplings(-0.2, tau)
+    _say(f"case: routes tau={tau}: liquid-only gw_A=-0.2 cos {eq['cos_liquid_route']:.4f}; "
+         f"gas-only gw_B={eq['gw_gas']:.4f} cos {eq['cos_gas_route']:.4f}")
+    assert abs(eq["cos_gas_route"] - eq["cos_liquid_route"]) <= 0.01
+    geom = inputs.Geometry(900, 42, 300, 600)
+    cases = [inputs.Case(geom, inputs.Params(G=0.9, gw=gw, tau=tau), seed=1)
+             for gw in [(-0.2, 0.0), (0.0, eq["gw_gas"]), (-0.2, 0.2)]]
+    b = Batch(cases, sample_every=500, max_samples=81)
+    b.set_tile(128, 16, graph_steps=100, order=1, fuse=2)
+    b.step(40000)
+    recs, ns = b.observe()
+    t = np.arange(ns) * 500.0
+    z = [np.array([r["z"] for r in recs[c][:ns]]) for c in range(3)]
+    assert all(recs[c][ns - 1]["flags"] == 0 for c in range(3))
+    late = t >= 20000
+    s = [np.polyfit(t[late], zz[late], 1)[0] for zz in z]
+    diff = np.abs(z[0] - z[1]).max()
+    _say(f"  late speeds {s[0]:.3e} {s[1]:.3e} (both walls {s[2]:.3e}); max|dz| {diff:.2f} of {z[0].max():.1f}")
+    assert 0.9 <= s[1] / s[0] <= 1.1
+    assert diff <= 0.06 * z[0].max()
+    assert s[2] > 1.5 * s[0]            # coupling both components wets more strongly

@@ -7,6 +7,7 @@ import os
 import sys
 
 import numpy as np
+import pytest
 
 from paper_0807_0602_amd import inputs
 
@@ -104,3 +105,33 @@ def test_bench_counter_summary(tmp_path, monkeypatch):
     t = json.load(open(tmp_path / "traffic.json"))
     assert len(t["schedules"]) == 2
     assert bench.measured_traffic(cells, {"bx": 256, "cy": 16, "order": 1, "fuse": 2}) == (900000 * 2 + 1179000) * 1024
+
+
+def test_wetting_circle_fit_and_contour():
+    """Host analysis of the sessile-droplet estimator on a synthetic circular cap: the contour
+    points of a signed-distance field and the algebraic circle fit recover the cap's angle."""
+    from paper_0807_0602_amd import wetting as W
+    ny, nx = 60, 120
+    xc, yc, R = 59.5, -6.0, 30.0            # centre below the wall plane y = 0.5: angle < 90
+    Y, X = np.meshgrid(np.arange(ny), np.arange(nx), indexing="ij")
+    phi = R - np.hypot(X - xc, Y - yc)
+    phi[0, :] = -1.0
+    pts = W._contour_points(phi, 5)
+    cx, cy, cr = W.fit_circle(pts)
+    assert abs(cx - xc) < 0.05 and abs(cy - yc) < 0.05 and abs(cr - R) < 0.05
+    assert abs((0.5 - cy) / cr - (0.5 - yc) / R) < 2e-3
+    # exact circle through three points
+    t = np.array([0.3, 1.7, 2.9])
+    p3 = np.stack([2 + 5 * np.cos(t), -1 + 5 * np.sin(t)], axis=1)
+    assert np.allclose(W.fit_circle(p3), (2.0, -1.0, 5.0))
+
+
+def test_wetting_match_and_pressure():
+    from oracle import physics
+    from paper_0807_0602_amd import wetting as W
+    assert W.match_coupling([0.1, 0.2, 0.3], [0.1, 0.2, 0.35], 0.275) == pytest.approx(0.25)
+    with pytest.raises(ValueError):
+        W.match_coupling([0.1, 0.2], [0.1, 0.2], 0.5)
+    rng = np.random.default_rng(3)
+    a, b = rng.uniform(0, 2, 50), rng.uniform(0, 2, 50)
+    assert np.allclose(W.eos_pressure(a, b, 0.9), physics.pressure(a, b, 0.9))
