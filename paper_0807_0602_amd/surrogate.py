@@ -171,8 +171,7 @@ def simulate(cases: Sequence[Case], steps: int, every: int, group: int = 64, log
     for g0 in range(0, len(cases), group):
         part = list(cases[g0:g0 + group])
         b = Batch(part, sample_every=every, max_samples=ns)
-        t = b.tile()
-        b.set_tile(t["bx"], 8, every, 1)
+        b.set_tile(256, 16, every, 3, 2)   # two steps per launch (the sweep's autotuned schedule)
         b.step(steps)
         recs, k = b.observe(allow_unstable=True)
         for c, r in enumerate(recs):
