@@ -8,7 +8,8 @@ gamma cos(theta) is measured independently from a static meniscus at the same pa
 (mu = sum_k rho_k nu_k, Sec. 2).  The late-window fit must be linear (R^2 >= 0.9995) with a slope
 between 0.70 and 1.05 of the static prediction: a moving contact line has a larger (dynamic)
 angle than the static one (measured on the 200 x 24 capillary: cos 0.345 moving vs 0.475 static),
-which lowers the slope.  The precursor film stays ahead of the centre-line front.
+which lowers the slope.  The precursor film stays ahead of the centre-line front and its lead
+grows sub-linearly in time.
 """
 import sys
 
@@ -83,6 +84,12 @@ def test_drag_corrected_front_law(scf, tau):
          f"ratio={coef[0] / pred:.3f} R2={r2:.6f} z(150k)={zl:.1f}")
     assert r2 >= 0.9995
     assert 0.70 <= coef[0] / pred <= 1.05
-    # the precursor film leads the centre-line front once formed (P12)
+    # the precursor film leads the centre-line front once formed, and its lead grows
+    # sub-linearly in time (Sec. 3: a film ahead of the meniscus growing like a power of t
+    # below one)
     late = (ts >= 20_000) & np.isfinite(ps)
     assert np.all(ps[late] > zs[late])
+    d = ps[late] - zs[late]
+    beta = np.polyfit(np.log(ts[late]), np.log(d), 1)[0]
+    _say(f"  precursor lead {d[0]:.2f} -> {d[-1]:.2f} lu, power of t {beta:.3f}")
+    assert d[-1] > d[0] and 0.0 < beta < 0.9
