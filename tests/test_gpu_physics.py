@@ -89,7 +89,7 @@ def test_drag_corrected_front_law(scf, tau):
     # centre turns to gas the film level is no longer defined); in this partial-wetting,
     # equal-viscosity channel the lead stays nearly constant, so it shrinks relative to the
     # distance filled
-    late = (ts >= 20_000) & np.isfinite(ps) & (fl == 0)
+    late = (ts >= 40_000) & np.isfinite(ps) & (fl == 0) & (zs > 0)
     assert late.sum() >= 50
     d = ps[late] - zs[late]
     _say(f"  precursor lead {d[0]:.2f} -> {d[-1]:.2f} lu while z {zs[late][0]:.1f} -> {zs[late][-1]:.1f}")
