@@ -108,6 +108,7 @@ class Case:
     params: Params
     rho_liq: float = 2.0      # majority density of each component in its own phase
     rho_min: float = 0.06     # minority (dissolved) density
+    gas: Optional[Tuple[float, float]] = None   # (n_A, n_B) of the B-rich phase if not symmetric
     liquid_x1: Optional[int] = None   # liquid A fills x < liquid_x1 (default x0)
     noise: float = 1e-3
     seed: int = 1
@@ -125,8 +126,9 @@ class Case:
         Y, X = np.meshgrid(ys, xs_glob, indexing="ij")
         lx1 = g.x0 if self.liquid_x1 is None else self.liquid_x1
         liquid = X < lx1
-        rhoA = np.where(liquid, self.rho_liq, self.rho_min).astype(np.float64)
-        rhoB = np.where(liquid, self.rho_min, self.rho_liq).astype(np.float64)
+        gA, gB = self.gas if self.gas is not None else (self.rho_min, self.rho_liq)
+        rhoA = np.where(liquid, self.rho_liq, gA).astype(np.float64)
+        rhoB = np.where(liquid, self.rho_min, gB).astype(np.float64)
         if self.noise:
             rhoA = rhoA + self.noise * uniform_pm1(self.seed, 0, Y, X)
             rhoB = rhoB + self.noise * uniform_pm1(self.seed, 1, Y, X)
@@ -248,13 +250,16 @@ def slab_fields(case: Case) -> Tuple[np.ndarray, np.ndarray]:
 
 
 def droplet_fields(n: int, R: float, rho_liq: float = 2.0, rho_min: float = 0.06,
-                   noise: float = 0.0, seed: int = 0) -> Tuple[np.ndarray, np.ndarray]:
-    """Periodic n x n box, a disc of A of radius R centred at ((n-1)/2, (n-1)/2) in B."""
+                   noise: float = 0.0, seed: int = 0,
+                   gas: Optional[Tuple[float, float]] = None) -> Tuple[np.ndarray, np.ndarray]:
+    """Periodic n x n box, a disc of A of radius R centred at ((n-1)/2, (n-1)/2) in B.
+    `gas`: (n_A, n_B) outside the disc, default (rho_min, rho_liq)."""
     c = (n - 1) / 2.0
     Y, X = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
     inside = (X - c) ** 2 + (Y - c) ** 2 < R * R
-    rhoA = np.where(inside, rho_liq, rho_min).astype(np.float64)
-    rhoB = np.where(inside, rho_min, rho_liq).astype(np.float64)
+    gA, gB = gas if gas is not None else (rho_min, rho_liq)
+    rhoA = np.where(inside, rho_liq, gA).astype(np.float64)
+    rhoB = np.where(inside, rho_min, gB).astype(np.float64)
     if noise:
         rhoA = rhoA + noise * uniform_pm1(seed, 0, Y, X)
         rhoB = rhoB + noise * uniform_pm1(seed, 1, Y, X)
@@ -262,12 +267,14 @@ def droplet_fields(n: int, R: float, rho_liq: float = 2.0, rho_min: float = 0.06
 
 
 def plug_fields(geom: Geometry, xa: int, xb: int, rho_liq: float = 2.0,
-                rho_min: float = 0.06) -> Tuple[np.ndarray, np.ndarray]:
-    """A plug of A for x in [xa, xb) in a channel; B elsewhere; solid nodes zero."""
+                rho_min: float = 0.06, gas: Optional[Tuple[float, float]] = None) -> Tuple[np.ndarray, np.ndarray]:
+    """A plug of A for x in [xa, xb) in a channel; B elsewhere (composition `gas`, default
+    (rho_min, rho_liq)); solid nodes zero."""
     Y, X = np.meshgrid(np.arange(geom.ny), np.arange(geom.nx), indexing="ij")
     inside = (X >= xa) & (X < xb)
-    rhoA = np.where(inside, rho_liq, rho_min).astype(np.float64)
-    rhoB = np.where(inside, rho_min, rho_liq).astype(np.float64)
+    gA, gB = gas if gas is not None else (rho_min, rho_liq)
+    rhoA = np.where(inside, rho_liq, gA).astype(np.float64)
+    rhoB = np.where(inside, rho_min, gB).astype(np.float64)
     solid = geom.solid_mask()
     rhoA[solid] = 0.0
     rhoB[solid] = 0.0
@@ -275,13 +282,15 @@ def plug_fields(geom: Geometry, xa: int, xb: int, rho_liq: float = 2.0,
 
 
 def sessile_fields(geom: Geometry, xc: float, R: float, rho_liq: float = 2.0,
-                   rho_min: float = 0.06) -> Tuple[np.ndarray, np.ndarray]:
+                   rho_min: float = 0.06, gas: Optional[Tuple[float, float]] = None) -> Tuple[np.ndarray, np.ndarray]:
     """A half-disc of A of radius R centred at (xc, 0.5) on the bottom wall plane (between the
-    solid row 0 and the first fluid row), B elsewhere; solid nodes zero."""
+    solid row 0 and the first fluid row), B elsewhere (composition `gas`, default
+    (rho_min, rho_liq)); solid nodes zero."""
     Y, X = np.meshgrid(np.arange(geom.ny), np.arange(geom.nx), indexing="ij")
     inside = (X - xc) ** 2 + (Y - 0.5) ** 2 < R * R
-    rhoA = np.where(inside, rho_liq, rho_min).astype(np.float64)
-    rhoB = np.where(inside, rho_min, rho_liq).astype(np.float64)
+    gA, gB = gas if gas is not None else (rho_min, rho_liq)
+    rhoA = np.where(inside, rho_liq, gA).astype(np.float64)
+    rhoB = np.where(inside, rho_min, gB).astype(np.float64)
     solid = geom.solid_mask()
     rhoA[solid] = 0.0
     rhoB[solid] = 0.0

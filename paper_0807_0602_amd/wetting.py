@@ -13,8 +13,9 @@ independent estimators:
   n_A = n_B contour away from the wall) meets the wall plane - half a node inside the solid row,
   where half-way bounce-back puts it - at the contact angle: cos(theta) = (y_wall - y_c) / R.
 
-The pressure is the model's equation of state for alpha = 4/9 and the force weights of the
-build (reading of Sec. 2): p = (n_A + n_B)/3 + (G/3) n_A n_B.
+The pressure is the model's equation of state with the force weights of the build (reading of
+Sec. 2): p = sum_k m_k n_k c_k^2 + (G/3) n_A n_B with c_k^2 = 3 (1 - alpha_k) / 5, the second
+moment of eqs. feq1-feq3; at alpha = 4/9 and m = 1 it is (n_A + n_B)/3 + (G/3) n_A n_B.
 
 `contact_angle_map` tabulates both estimators over wall couplings and relaxation-time pairs;
 `match_coupling` inverts a table, e.g. to find the repulsive gas coupling that gives the same
@@ -36,9 +37,12 @@ from .scf import Batch
 Pair = Tuple[float, float]
 
 
-def eos_pressure(nA: np.ndarray, nB: np.ndarray, G: float) -> np.ndarray:
-    """Pressure of the binary mixture at rest fraction 4/9: (n_A + n_B)/3 + (G/3) n_A n_B."""
-    return (nA + nB) / 3.0 + (G / 3.0) * nA * nB
+def eos_pressure(nA: np.ndarray, nB: np.ndarray, G: float, alpha: Pair = (4.0 / 9.0, 4.0 / 9.0),
+                 mass: Pair = (1.0, 1.0)) -> np.ndarray:
+    """Pressure of the binary mixture: sum_k m_k n_k 3 (1 - alpha_k)/5 + (G/3) n_A n_B."""
+    cA = 3.0 * (1.0 - alpha[0]) / 5.0
+    cB = 3.0 * (1.0 - alpha[1]) / 5.0
+    return mass[0] * cA * nA + mass[1] * cB * nB + (G / 3.0) * nA * nB
 
 
 def _run(cases: Sequence[Case], fields, steps: int, fuse: int = 2):
@@ -57,21 +61,23 @@ def _run(cases: Sequence[Case], fields, steps: int, fuse: int = 2):
 
 # ------------------------------------------------------------------------------ surface tension
 def laplace_tension(tau: Pair = (1.0, 1.0), G: float = 0.9, radii: Sequence[float] = (10, 14, 18, 22),
-                    n: int = 96, steps: int = 8000) -> Dict:
+                    n: int = 96, steps: int = 8000, alpha: Pair = (4.0 / 9.0, 4.0 / 9.0),
+                    mass: Pair = (1.0, 1.0), rho: Pair = (2.0, 0.06), gas: Optional[Pair] = None) -> Dict:
     """gamma from Laplace's law on free droplets of A in periodic n x n boxes: least-squares
     fit of Delta p = p_in - p_out against 1/R, R from the droplet area (nodes with
-    n_A > n_B).  Returns gamma, the intercept and the per-droplet data."""
+    n_A > n_B).  `rho`: initial (majority, minority) densities of the drop, `gas`: initial
+    (n_A, n_B) around it.  Returns gamma, the intercept and the per-droplet data."""
     geom = Geometry(n, n, 0, 0)
-    prm = Params(G=G, gw=(0.0, 0.0), tau=tuple(tau))
+    prm = Params(G=G, gw=(0.0, 0.0), tau=tuple(tau), alpha=tuple(alpha), mass=tuple(mass))
     cases = [Case(geom, prm, noise=0.0, name=f"droplet_R{R}") for R in radii]
-    fields = [inputs.droplet_fields(n, R) for R in radii]
+    fields = [inputs.droplet_fields(n, R, rho_liq=rho[0], rho_min=rho[1], gas=gas) for R in radii]
     res = _run(cases, fields, steps)
     dps, Rs = [], []
     c = (n - 1) / 2.0
     Y, X = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
     r = np.hypot(X - c, Y - c)
     for (nA, nB, _), R0 in zip(res, radii):
-        p = eos_pressure(nA, nB, G)
+        p = eos_pressure(nA, nB, G, alpha, mass)
         R = np.sqrt(np.count_nonzero(nA > nB) / np.pi)
         p_in = p[r < 0.5 * R].mean()
         p_out = p[r > R + 0.35 * (n / 2 - R)].mean()
@@ -88,22 +94,28 @@ class WallCase:
     gw: Pair
     tau: Pair = (1.0, 1.0)
     G: float = 0.9
+    alpha: Pair = (4.0 / 9.0, 4.0 / 9.0)
+    mass: Pair = (1.0, 1.0)
+
+    def params(self) -> Params:
+        return Params(G=self.G, gw=self.gw, tau=self.tau, alpha=self.alpha, mass=self.mass)
 
 
 def meniscus_cos(cases: Sequence[WallCase], gamma: float, H: int = 40, L: int = 320,
-                 steps: int = 30000) -> List[Dict]:
+                 steps: int = 30000, rho: Pair = (2.0, 0.06), gas: Optional[Pair] = None) -> List[Dict]:
     """Static-meniscus estimator: a plug of A over the middle half of a fully walled periodic
     channel (L x H fluid rows); cos(theta) = H (p_gas - p_liq) / (2 gamma), pressures averaged
     over the middle of the plug and of the gas, away from walls and menisci."""
     geom = Geometry(L, H + 2, 0, L)
-    cs = [Case(geom, Params(G=w.G, gw=w.gw, tau=w.tau), noise=0.0) for w in cases]
-    fields = [inputs.plug_fields(geom, L // 4, 3 * L // 4) for _ in cases]
+    cs = [Case(geom, w.params(), noise=0.0) for w in cases]
+    fields = [inputs.plug_fields(geom, L // 4, 3 * L // 4, rho_liq=rho[0], rho_min=rho[1], gas=gas)
+              for _ in cases]
     res = _run(cs, fields, steps)
     rows = slice(1 + H // 4, 1 + 3 * H // 4)
     q = L // 16
     out = []
     for w, (nA, nB, flags) in zip(cases, res):
-        p = eos_pressure(nA, nB, w.G)
+        p = eos_pressure(nA, nB, w.G, w.alpha, w.mass)
         p_liq = p[rows, L // 2 - q:L // 2 + q].mean()
         p_gas = np.concatenate([p[rows, :q], p[rows, L - q:]], axis=1).mean()
         dp = p_gas - p_liq
@@ -138,13 +150,15 @@ def fit_circle(pts: np.ndarray) -> Tuple[float, float, float]:
 
 
 def sessile_cos(cases: Sequence[WallCase], R: float = 24.0, nx: int = 160, ny: int = 72,
-                steps: int = 30000, skip: int = 4) -> List[Dict]:
+                steps: int = 30000, skip: int = 4, rho: Pair = (2.0, 0.06),
+                gas: Optional[Pair] = None) -> List[Dict]:
     """Sessile-droplet estimator: a half-disc of A of radius R on the bottom wall of a fully
     walled channel (periodic in x), relaxed for `steps`; a circle fitted to the interface points
     at least `skip` nodes above the wall gives cos(theta) = (0.5 - y_c) / R_fit."""
     geom = Geometry(nx, ny, 0, nx)
-    cs = [Case(geom, Params(G=w.G, gw=w.gw, tau=w.tau), noise=0.0) for w in cases]
-    fields = [inputs.sessile_fields(geom, (nx - 1) / 2.0, R) for _ in cases]
+    cs = [Case(geom, w.params(), noise=0.0) for w in cases]
+    fields = [inputs.sessile_fields(geom, (nx - 1) / 2.0, R, rho_liq=rho[0], rho_min=rho[1], gas=gas)
+              for _ in cases]
     res = _run(cs, fields, steps)
     out = []
     for w, (nA, nB, flags) in zip(cases, res):

@@ -104,3 +104,18 @@ def test_two_wetting_routes_fill_alike(W, tau):
     assert 0.9 <= s[1] / s[0] <= 1.1
     assert diff <= 0.06 * z[0].max()
     assert s[2] > 1.5 * s[0]            # coupling both components wets more strongly
+
+
+def test_density_ratio_droplets_obey_laplace(W):
+    """Unequal sound speeds (alpha = 0.8 for the drop, 4/9 around it) with the paper's
+    relaxation times for its water-in-air runs (tau = 2.5 and 0.626, i.e. nu = 0.667 and 0.042,
+    labels as read): static drops hold a density ratio above 2.2 and follow Laplace's law with
+    the pressure of unequal sound speeds."""
+    al, tau, G = (0.8, 4.0 / 9.0), (2.5, 0.626), 1.5
+    lt = W.laplace_tension(tau, G, alpha=al, rho=(1.25, 0.005), gas=(0.17, 0.31), steps=20000)
+    dpR = np.asarray(lt["dp"]) * np.asarray(lt["R"])
+    _say(f"  density-ratio drops: gamma {lt['gamma']:.5f} intercept {lt['intercept']:.2e} "
+         f"spread {dpR.std() / dpR.mean():.3%}")
+    assert dpR.std() / dpR.mean() <= 0.03
+    assert abs(lt["intercept"]) <= 0.1 * lt["dp"][-1]
+    assert 0.02 < lt["gamma"] < 0.1

@@ -31,6 +31,34 @@ def test_flat_interface_rest_and_coexistence():
 
 
 @pytest.mark.slow
+def test_unequal_sound_speeds_flat_interface():
+    """Components with different rest fractions (Sec. 3: alpha_1 = 4/9, alpha_2 = 0.8 gives the
+    heavier component the lower sound speed, eqs. feq1-feq3) coexist across a flat interface
+    with unequal densities; mechanical equilibrium then holds for the pressure built from the
+    equilibrium's second moment, p = sum_k m_k n_k 3(1 - alpha_k)/5 + (G/3) n_A n_B, and not for
+    the equal-sound-speed form."""
+    nx, ny, G = 128, 4, 1.5
+    al, m = (0.8, 4.0 / 9.0), (1.0, 1.0)
+    X = np.arange(nx)[None, :].repeat(ny, 0)
+    liq = (X >= 32) & (X < 96)
+    a = np.where(liq, 1.0, 0.05).astype(float)
+    b = np.where(liq, 0.05, 0.34).astype(float)
+    oracle.set_threads(8)
+    o = oracle.Oracle(nx, ny, 0, 0, G, (0.0, 0.0), (1.0, 1.0), alpha=al, mass=m).init(a, b)
+    o.step(20000)
+    A, B = o.density()
+    la, lb, ga, gb = A[0, 64], B[0, 64], A[0, 0], B[0, 0]
+    assert (la + lb) / (ga + gb) > 2.2          # a density ratio, from the sound speeds alone
+
+    def p(nA, nB, alpha):
+        return (m[0] * nA * 3 * (1 - alpha[0]) / 5 + m[1] * nB * 3 * (1 - alpha[1]) / 5
+                + G / 3 * nA * nB)
+
+    assert abs(p(la, lb, al) - p(ga, gb, al)) <= 1e-4 * p(la, lb, al)
+    eq = (4.0 / 9.0, 4.0 / 9.0)
+    assert abs(p(la, lb, eq) - p(ga, gb, eq)) > 0.05 * p(la, lb, eq)
+
+
 def test_laplace_law():
     n = 96
     rows = []
