@@ -84,13 +84,15 @@ def test_drag_corrected_front_law(scf, tau):
          f"ratio={coef[0] / pred:.3f} R2={r2:.6f} z(150k)={zl:.1f}")
     assert r2 >= 0.9995
     assert 0.70 <= coef[0] / pred <= 1.05
-    # the precursor film (wall rows, n_A above a third of the reservoir's bulk value) leads the
-    # centre-line front while the liquid reservoir lasts (flag bit 0 clear: once the reservoir
-    # centre turns to gas the film level is no longer defined); in this partial-wetting,
-    # equal-viscosity channel the lead stays nearly constant, so it shrinks relative to the
-    # distance filled
-    late = (ts >= 40_000) & np.isfinite(ps) & (fl == 0) & (zs > 0)
-    assert late.sum() >= 50
+    # the precursor film (wall rows, n_A above a third of the reservoir's bulk value, read at
+    # the reservoir centre x0/2) leads the centre-line front while that reading is bulk liquid:
+    # the channel draws the reservoir's far interface towards its centre, which it reaches once
+    # about x0/2 * ny nodes of liquid (z ~ x0/2 * ny / H) have entered, so only fronts below 70 %
+    # of that are used.  In this partial-wetting, equal-viscosity channel the lead stays nearly
+    # constant, so it shrinks relative to the distance filled.
+    z_res = 0.7 * (g.x0 / 2) * g.ny / H
+    late = (ts >= 40_000) & np.isfinite(ps) & (fl == 0) & (zs > 0) & (zs < z_res)
+    assert late.sum() >= 40
     d = ps[late] - zs[late]
     _say(f"  precursor lead {d[0]:.2f} -> {d[-1]:.2f} lu while z {zs[late][0]:.1f} -> {zs[late][-1]:.1f}")
     assert np.all(d > 0)
