@@ -273,8 +273,8 @@ def main() -> int:
             raise SystemExit("--summarize-counters needs --tile BX CY ORDER")
         return summarize_counters(args)
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on exactly one GPU; multi-GPU runs are not part of this build "
-              "(the channel would be split into x-slabs with a halo exchange per step).",
+        print("bench.py runs on exactly one GPU: the library has no multi-GPU path (a channel "
+              "would be split into x-slabs with a halo exchange per step or pass).",
               file=sys.stderr, flush=True)
         return 2
 
