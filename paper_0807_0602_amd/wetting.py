@@ -76,7 +76,10 @@ def laplace_tension(tau: Pair = (1.0, 1.0), G: float = 0.9, radii: Sequence[floa
     c = (n - 1) / 2.0
     Y, X = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
     r = np.hypot(X - c, Y - c)
-    for (nA, nB, _), R0 in zip(res, radii):
+    for (nA, nB, flags), R0 in zip(res, radii):
+        if flags & 2 or not (np.isfinite(nA).all() and np.isfinite(nB).all()):
+            raise RuntimeError(f"droplet R = {R0} went unstable (flags {flags}); start closer to "
+                               "the coexisting compositions or change tau")
         p = eos_pressure(nA, nB, G, alpha, mass)
         R = np.sqrt(np.count_nonzero(nA > nB) / np.pi)
         p_in = p[r < 0.5 * R].mean()
