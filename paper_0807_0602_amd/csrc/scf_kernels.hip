@@ -379,9 +379,10 @@ k_step_fused(const Chan* __restrict__ chans, const TileDesc* __restrict__ tiles,
 // pulls row yb-3+k, stage 1 collides row yb-4+k, stage 2 pulls row yb-5+k and collides and
 // stores row yb-6+k.  Three barriers per row: after the stage-1 densities, after the edge
 // values, after the stage-2 densities.  Each node is computed with exactly the arithmetic of
-// the single step, so two stages equal two single steps bit for bit.  The kernel is held to
-// three waves per SIMD (at most 168 VGPRs, no spills): faster than two waves with the
-// registers it would otherwise take, and than four with spills.
+// the single step, so two stages equal two single steps bit for bit.  The stage-1 loads of the
+// next row are issued after the second barrier, so their latency overlaps stage 2.  The
+// kernel is held to three waves per SIMD (at most 168 VGPRs, a few spilled): faster than two
+// waves with the registers it would otherwise take, and than four with more spills.
 // ---------------------------------------------------------------------------------------------
 struct RegOut {
     float* r;
@@ -447,22 +448,30 @@ k_step_fused2(const Chan* __restrict__ chans, const TileDesc* __restrict__ tiles
         uint32_t qcode = 0;
         // stage 2: shifted f*(t) of the last two stage-1 rows (dirs 0,1,3,2,5,6 and 2,5,6 per
         // component), own unshifted f*(t) of the last row, pulled row awaiting collision
-        float gm1[12], gm2[6], uf[18], q2[18];
+        float gm1[12], gm2[6], uf[14], q2[18];   // uf: directions 1,3,4,5,6,7,8 per component
         float q2A = 0.0f, q2B = 0.0f;
         uint32_t q2code = 0;
 #pragma unroll
-        for (int i = 0; i < 18; ++i) q[i] = uf[i] = q2[i] = 0.0f;
+        for (int i = 0; i < 18; ++i) q[i] = q2[i] = 0.0f;
+#pragma unroll
+        for (int i = 0; i < 14; ++i) uf[i] = 0.0f;
 #pragma unroll
         for (int i = 0; i < 12; ++i) gm1[i] = 0.0f;
 #pragma unroll
         for (int i = 0; i < 6; ++i) gm2[i] = 0.0f;
         const int niter = td.ye - td.yb + 6;
+        // the stage-1 pull of row a + 1 is issued during iteration k (after the second barrier)
+        // so that its latency overlaps the stage-2 work of the row
+        float pn[18];
+        uint32_t pcode = pull_node_buf<MASK>(rs, Pb, c, ws, x, wrap_mod(td.yb - 3, c.ny), pn);
         for (int k = 0; k < niter; ++k) {
             const int s0 = k % 3, s1 = (k + 2) % 3, s2 = (k + 1) % 3;   // iterations k, k-1, k-2
-            // A: stage-1 pull of row a, densities n(t) into r1
+            // A: stage-1 pull of row a (issued one iteration ago), densities n(t) into r1
             const int a = wrap_mod(td.yb - 3 + k, c.ny);
             float p[18];
-            const uint32_t code = pull_node_buf<MASK>(rs, Pb, c, ws, x, a, p);
+#pragma unroll
+            for (int i = 0; i < 18; ++i) p[i] = pn[i];
+            const uint32_t code = pcode;
             float nA = 0.0f, nB = 0.0f;
             if (!(code & 1u)) {
                 nA = sum9(p);
@@ -526,6 +535,7 @@ k_step_fused2(const Chan* __restrict__ chans, const TileDesc* __restrict__ tiles
                 g[3] = eL[wv + 1][0]; g[6] = eL[wv + 1][1]; g[7] = eL[wv + 1][2];
                 g[12] = eL[wv + 1][3]; g[15] = eL[wv + 1][4]; g[16] = eL[wv + 1][5];
             }
+            if (k + 1 < niter) pcode = pull_node_buf<MASK>(rs, Pb, c, ws, x, a == c.ny - 1 ? 0 : a + 1, pn);
             // C: stage-2 pull of row b = a - 2: directions 0,1,3 from row b, 2,5,6 from row
             // b - 1, 4,7,8 from row b + 1 (this iteration's shifted values)
             float f2[18];
@@ -553,11 +563,15 @@ k_step_fused2(const Chan* __restrict__ chans, const TileDesc* __restrict__ tiles
                     f2[o + 8] = g[o + 8];
                 }
                 if (code2) {
+                    // own unshifted f*(t) of row b: direction 2 is the unshifted gm1 entry, the
+                    // others are kept in uf (slot of direction d: ufs[d])
+                    const int ufs[9] = {-1, 0, -1, 1, 2, 3, 4, 5, 6};
 #pragma unroll
                     for (int i = 1; i < 9; ++i)
                         if ((code2 >> opp[i]) & 1u) {
-                            f2[i] = uf[opp[i]];
-                            f2[9 + i] = uf[9 + opp[i]];
+                            const int d = opp[i];
+                            f2[i] = d == 2 ? gm1[3] : uf[ufs[d]];
+                            f2[9 + i] = d == 2 ? gm1[9] : uf[7 + ufs[d]];
                         }
                 }
                 if (!(code2 & 1u)) {
@@ -582,8 +596,17 @@ k_step_fused2(const Chan* __restrict__ chans, const TileDesc* __restrict__ tiles
 #pragma unroll
             for (int i = 0; i < 18; ++i) {
                 q[i] = p[i];
-                uf[i] = fs[i];
                 q2[i] = f2[i];
+            }
+#pragma unroll
+            for (int m = 0; m < 2; ++m) {
+                uf[7 * m + 0] = fs[9 * m + 1];
+                uf[7 * m + 1] = fs[9 * m + 3];
+                uf[7 * m + 2] = fs[9 * m + 4];
+                uf[7 * m + 3] = fs[9 * m + 5];
+                uf[7 * m + 4] = fs[9 * m + 6];
+                uf[7 * m + 5] = fs[9 * m + 7];
+                uf[7 * m + 6] = fs[9 * m + 8];
             }
             qA = nA;
             qB = nB;
