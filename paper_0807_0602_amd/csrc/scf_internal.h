@@ -54,7 +54,8 @@ struct ObsRec {
 struct TileDesc {
     int32_t chan, xb, yb, ye;   // strip [xb, xb+bx) x rows [yb, ye)
     int32_t down;               // 0: rows walked upward from yb, 1: downward from ye-1
-    int32_t pad[3];
+    int32_t w;                  // output columns of the strip (two-step tiles)
+    int32_t pad[2];
 };
 
 // Kernel launchers (all asynchronous on `stream`; return hipSuccess or the launch error).
@@ -62,7 +63,7 @@ struct TileDesc {
 hipError_t launch_init(const Chan* chans, const RowRef* rows, int nrows, float* ws, hipStream_t s);
 hipError_t launch_step_fused(int bx, bool masked, const Chan* chans, const TileDesc* tiles,
                              int ntiles, int grid, float* ws, int src, hipStream_t s);
-// Two time steps in one pass; the tiles' strips are bx - 4 columns wide (see k_step_fused2).
+// Two time steps in one pass; each tile carries its output width w <= bx - 4 (see k_step_fused2).
 hipError_t launch_step_fused2(int bx, bool masked, const Chan* chans, const TileDesc* tiles,
                               int ntiles, int grid, float* ws, int src, hipStream_t s);
 hipError_t launch_step_two_kernel(const Chan* chans, const RowRef* rows, int nrows, float* ws,

@@ -369,7 +369,7 @@ k_step_fused(const Chan* __restrict__ chans, const TileDesc* __restrict__ tiles,
 
 // ---------------------------------------------------------------------------------------------
 // Two time steps per pass (temporal blocking).  A block of BX lanes owns the output columns
-// [xb, xb + w), w <= BX - 4, and rows [yb, ye).  Stage 1 is the single step above on the wider
+// [xb, xb + w), w = the tile's width <= BX - 4, and rows [yb, ye).  Stage 1 is the single step above on the wider
 // window [xb - 2, xb + w + 2) (lane = column + 2 - xb), with the two density-halo columns
 // xb - 3 and xb + w + 2 pulled by lanes 0 and 1; its post-collision values f*(t) never leave
 // the chip.  Stage 2 streams them: the x part by whole-wave lane shifts (DPP; the lanes at a
@@ -432,7 +432,7 @@ k_step_fused2(const Chan* __restrict__ chans, const TileDesc* __restrict__ tiles
         const TileDesc td = tiles[t];
         if (td.ye <= td.yb) continue;
         const Chan c = chans[td.chan];
-        const int w = min(BX - 4, c.nx - td.xb);
+        const int w = min(td.w, c.nx - td.xb);
         const bool in1 = tid < w + 4;
         const bool in2 = tid >= 2 && tid < w + 2;
         const int x = wrap_mod(td.xb - 2 + min(tid, w + 3), c.nx);

@@ -217,6 +217,7 @@ struct Engine {
                     td.yb = k * chunk;
                     td.ye = std::min(td.yb + chunk, g.ny);
                     td.down = k & 1;
+                    td.w = bxv;
                     tl.push_back(td);
                 }
         }
@@ -235,9 +236,14 @@ struct Engine {
         return out;
     }
 
+    // Output columns per block of the two-step kernel: bx - 4 (it computes stage 1 on two
+    // extra columns each side), rounded down to 32 columns for 512-wide blocks so that strip
+    // edges fall on 128-byte lines (measured faster there; narrower blocks lose too much).
+    static int strip2(int bxv) { return bxv == 512 ? 480 : bxv - 4; }
+
     int upload_tiles(int bxv, int cyv, int ord) {
         std::vector<scf::TileDesc> tl = make_tiles(bxv, cyv, ord);
-        std::vector<scf::TileDesc> tl2 = make_tiles(bxv - 4, cyv, ord);
+        std::vector<scf::TileDesc> tl2 = make_tiles(strip2(bxv), cyv, ord);
         if ((int)tl.size() > lay.max_tiles || (int)tl2.size() > lay.max_tiles)
             return fail(SCF_EINVAL, "tile list exceeds its reserved space");
         HIP_TRY(hipMemcpyAsync(d_tiles(), tl.data(), sizeof(scf::TileDesc) * tl.size(),
@@ -461,7 +467,7 @@ struct Engine {
         int maxny = 0;
         for (auto& g : geom) maxny = std::max(maxny, g.ny);
         const int bxs[4] = {64, 128, 256, 512};
-        const int cys[8] = {4, 8, 16, 32, 48, 64, 128, 1 << 30};
+        const int cys[10] = {4, 8, 16, 24, 32, 40, 48, 64, 128, 1 << 30};
         hipEvent_t e0, e1;
         HIP_TRY(hipEventCreate(&e0));
         HIP_TRY(hipEventCreate(&e1));
