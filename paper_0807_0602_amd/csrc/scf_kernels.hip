@@ -158,8 +158,11 @@ __device__ __forceinline__ uint32_t pull_node_buf(__amdgpu_buffer_rsrc_t r, int 
     return 0u;
 }
 
-// Destinations of the post-collision populations: plain global stores or buffer stores, both
-// non-temporal (the values are not read again within the step).
+// Destinations of the post-collision populations: plain global stores or buffer stores.  The
+// single step's stores are non-temporal (the values are not read again within the step, and each
+// wave writes whole cache lines).  The two-step kernel stores through the cache: its lanes are
+// offset by two columns from the output strip, so each wave covers parts of three lines, and
+// non-temporal partial lines reached memory twice (85 instead of 72 written bytes per node).
 struct GlobalOut {
     float* d;
     int64_t P;
@@ -168,14 +171,17 @@ struct GlobalOut {
         __builtin_nontemporal_store(v, &d[q * P + idx]);
     }
 };
-struct BufferOut {
+template <int AUX>   // 2: non-temporal, 0: cached
+struct BufferOutT {
     __amdgpu_buffer_rsrc_t r;
     int Pb;
     int off;
     __device__ __forceinline__ void operator()(int q, float v) const {
-        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, off, q * Pb, 2);
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, off, q * Pb, AUX);
     }
 };
+using BufferOut = BufferOutT<2>;
+using BufferOutCached = BufferOutT<0>;
 
 __device__ __forceinline__ float sum9(const float* f) {
     float s = f[0];
@@ -591,7 +597,7 @@ k_step_fused2(const Chan* __restrict__ chans, const TileDesc* __restrict__ tiles
                 float swx = 0.0f, swy = 0.0f;
                 if (q2code) wall_sum(q2code, swx, swy);
                 collide_store(c, q2, q2A, q2B, sAx, sAy, sBx, sBy, swx, swy,
-                              BufferOut{rd, Pb, (yc * c.pitch + x) * 4});
+                              BufferOutCached{rd, Pb, (yc * c.pitch + x) * 4});
             }
 #pragma unroll
             for (int i = 0; i < 18; ++i) {
