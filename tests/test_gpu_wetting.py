@@ -115,7 +115,8 @@ def test_density_ratio_droplets_obey_laplace(W):
     lt = W.laplace_tension(tau, G, alpha=al, rho=(1.25, 0.005), gas=(0.17, 0.31), steps=20000)
     dpR = np.asarray(lt["dp"]) * np.asarray(lt["R"])
     _say(f"  density-ratio drops: gamma {lt['gamma']:.5f} intercept {lt['intercept']:.2e} "
-         f"spread {dpR.std() / dpR.mean():.3%}")
+         f"spread {dpR.std() / dpR.mean():.3%} smallest density {lt['min_density']:.2e}")
+    assert lt["min_density"] > -0.01
     assert dpR.std() / dpR.mean() <= 0.03
     assert abs(lt["intercept"]) <= 0.1 * lt["dp"][-1]
     assert 0.02 < lt["gamma"] < 0.1
