@@ -128,4 +128,4 @@ def test_fuse_rejects_bad_values(scf):
         ch.set_tile(256, 8, fuse=3)
     with pytest.raises(L.ScfError):
         ch.set_tile(256, 8, fuse=0)
-    assert ch.tile()["fuse"] == 1
+    assert ch.tile()["fuse"] == 2      # the default schedule, unchanged by rejected calls
