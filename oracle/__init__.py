@@ -19,7 +19,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liboracle.so")
-_SOURCES = [os.path.join(_HERE, "scf_oracle.c")]
+_SOURCES = [os.path.join(_HERE, "scf_oracle.c"), os.path.join(_HERE, "scf3d_oracle.c")]
 
 
 def build(force: bool = True) -> str:
@@ -74,6 +74,18 @@ def lib():
         L.orc_density.argtypes = [C.c_void_p, dp, dp]
         L.orc_observe.argtypes = [C.c_void_p, C.POINTER(Obs)]
         L.orc_feq.argtypes = [C.c_double, C.c_double, C.c_double, C.c_double, dp]
+        L.orc3_create.restype = C.c_void_p
+        L.orc3_create.argtypes = [C.c_int] * 7 + [C.c_double, dp, dp, dp]
+        L.orc3_destroy.argtypes = [C.c_void_p]
+        L.orc3_init.argtypes = [C.c_void_p, dp, dp]
+        L.orc3_step.argtypes = [C.c_void_p, C.c_int64]
+        L.orc3_time.restype = C.c_int64
+        L.orc3_time.argtypes = [C.c_void_p]
+        L.orc3_density.argtypes = [C.c_void_p, dp, dp]
+        L.orc3_get_f.argtypes = [C.c_void_p, dp]
+        L.orc3_set_f.argtypes = [C.c_void_p, dp]
+        L.orc3_observe.argtypes = [C.c_void_p, dp, dp]
+        L.orc3_feq.argtypes = [C.c_double] * 4 + [dp]
         _lib = L
     return _lib
 
@@ -179,3 +191,69 @@ class Oracle:
         o = Obs()
         lib().orc_observe(self._h, C.byref(o))
         return o.as_dict()
+
+
+# D3Q19 velocities in the oracle's order (scf3d_oracle.c)
+CX3 = np.array([0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0])
+CY3 = np.array([0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1])
+CZ3 = np.array([0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1])
+
+
+def feq3(n: float, ux: float, uy: float, uz: float) -> np.ndarray:
+    out = np.zeros(19)
+    lib().orc3_feq(float(n), float(ux), float(uy), float(uz), _dp(out))
+    return out
+
+
+class Oracle3:
+    """One 3-D box (D3Q19).  Arrays are (nz, ny, nx), x fastest."""
+
+    def __init__(self, nx, ny, nz, x0=0, x1=0, walls_y=True, walls_z=False, G=0.9, gw=(0.0, 0.0),
+                 tau=(1.0, 1.0), mass=(1.0, 1.0)):
+        self.nx, self.ny, self.nz = int(nx), int(ny), int(nz)
+        self._keep = [_d2(gw), _d2(tau), _d2(mass)]
+        self._h = lib().orc3_create(self.nx, self.ny, self.nz, int(x0), int(x1), int(bool(walls_y)),
+                                    int(bool(walls_z)), float(G), *[_dp(a) for a in self._keep])
+        if not self._h:
+            raise ValueError("oracle3: bad geometry")
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            lib().orc3_destroy(h)
+            self._h = None
+
+    def init(self, rhoA, rhoB) -> "Oracle3":
+        a = np.ascontiguousarray(rhoA, dtype=np.float64)
+        b = np.ascontiguousarray(rhoB, dtype=np.float64)
+        assert a.shape == (self.nz, self.ny, self.nx) and b.shape == a.shape
+        lib().orc3_init(self._h, _dp(a), _dp(b))
+        return self
+
+    def step(self, n: int = 1) -> "Oracle3":
+        lib().orc3_step(self._h, int(n))
+        return self
+
+    @property
+    def t(self) -> int:
+        return int(lib().orc3_time(self._h))
+
+    def density(self):
+        a = np.zeros((self.nz, self.ny, self.nx)); b = np.zeros_like(a)
+        lib().orc3_density(self._h, _dp(a), _dp(b))
+        return a, b
+
+    def populations(self) -> np.ndarray:
+        f = np.zeros((2, 19, self.nz, self.ny, self.nx))
+        lib().orc3_get_f(self._h, _dp(f))
+        return f
+
+    def set_populations(self, f) -> None:
+        f = np.ascontiguousarray(f, dtype=np.float64)
+        assert f.shape == (2, 19, self.nz, self.ny, self.nx)
+        lib().orc3_set_f(self._h, _dp(f))
+
+    def observe(self) -> dict:
+        m = np.zeros(2); z = np.zeros(1)
+        lib().orc3_observe(self._h, _dp(m), _dp(z))
+        return {"t": self.t, "mass": (m[0], m[1]), "z": float(z[0])}

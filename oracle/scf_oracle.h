@@ -62,6 +62,23 @@ void orc_observe(orc_t*, orc_obs* out);
 /* Equilibrium of eqs. feq1-feq3 for one node. */
 void orc_feq(double n, double ux, double uy, double alpha, double out[9]);
 
+/* Three-dimensional D3Q19 counterpart (scf3d_oracle.c): box nx*ny*nz periodic in x, y, z;
+ * solid nodes for x in [x0, x1) on the planes y = 0, ny-1 (walls_y) and z = 0, nz-1 (walls_z).
+ * Arrays are nz*ny*nx (x fastest); populations f[k][i][z][y][x], i = 0..18 in the order of
+ * the C arrays CX3, CY3, CZ3 of scf3d_oracle.c. */
+typedef struct orc3 orc3_t;
+orc3_t* orc3_create(int nx, int ny, int nz, int x0, int x1, int walls_y, int walls_z, double G,
+                    const double gw[2], const double tau[2], const double mass[2]);
+void orc3_destroy(orc3_t*);
+void orc3_init(orc3_t*, const double* rhoA, const double* rhoB);
+void orc3_step(orc3_t*, int64_t nsteps);
+int64_t orc3_time(const orc3_t*);
+void orc3_density(orc3_t*, double* nA, double* nB);
+void orc3_get_f(const orc3_t*, double* f);
+void orc3_set_f(orc3_t*, const double* f);
+void orc3_observe(orc3_t*, double mass[2], double* z_front);
+void orc3_feq(double n, double ux, double uy, double uz, double out[19]);
+
 #ifdef __cplusplus
 }
 #endif
