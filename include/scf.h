@@ -280,6 +280,66 @@ int scf_sur_predict(scf_sur* s, const float* X, int64_t n, float* Y, uint8_t* in
 
 void scf_sur_destroy(scf_sur* s);
 
+/* ---------------------------------------------------------------------------------------------
+ * Three-dimensional capillary (D3Q19), the extension the paper names as future work
+ * (Conclusions).  The step is that of Sec. 2 on the D3Q19 lattice: equilibrium
+ * w_i n (1 + 3 c.u + 9/2 (c.u)^2 - 3/2 u.u) with w = 1/3 (rest), 1/18 (6 axis links), 1/36
+ * (12 edge links); bulk and wall forces of eqs. forcing and forcingw with the same link weights;
+ * common velocity, shifted equilibrium, BGK, pull streaming with half-way bounce-back.  The
+ * weights' z-projection is D2Q9 with rest fraction 4/9, so a z-independent state evolves as the
+ * 2-D model.  Two kernels per step (densities, then pull + collide), FP32 state.
+ * ------------------------------------------------------------------------------------------- */
+
+typedef struct {
+    int32_t nx, ny, nz;     /* box, periodic in x, y and z; 3 <= nx < 2^20, 3 <= ny, nz <= 65535 */
+    int32_t x0, x1;         /* the capillary occupies x in [x0, x1) */
+    int32_t walls_y;        /* non-zero: solid planes y = 0 and y = ny-1 over the capillary (a slit) */
+    int32_t walls_z;        /* non-zero: solid planes z = 0 and z = nz-1 too (a square duct) */
+} scf3_geometry;
+
+typedef struct {
+    int64_t t;
+    double mass[2];         /* sum of n_k over fluid nodes (FP64) */
+    double z;               /* front on the centre line (the up to four lines nearest
+                               y = (ny-1)/2, z = (nz-1)/2, averaged): first downward crossing of
+                               n_A - n_B scanning from x0/2, relative to x0; NaN if none */
+    int32_t flags;          /* as scf_obs.flags */
+    int32_t reserved;
+} scf3_obs;
+
+typedef struct scf3_ctx scf3_ctx;
+
+/* Device workspace for one 3-D box: two FP32 population buffers (2 x 2 x 19 planes), a 2-plane
+ * density field, per-row partial sums and one record; a plane is nz*ny rows of nx rounded up to
+ * 64 floats.  0 if the geometry is invalid. */
+size_t scf3_workspace_bytes(const scf3_geometry* geom);
+
+/* Create a 3-D context at rest equilibrium.  params->alpha must be 4/9 for both components (the
+ * D3Q19 equilibrium has fixed weights); G, gw, tau and mass as in scf_params.  rhoA, rhoB: host
+ * FP64 nz*ny*nx arrays (x fastest), copied.  Workspace and stream as for scf_init.  Synchronises.
+ * Errors: SCF_EINVAL, SCF_ENOMEM, SCF_EDEVICE. */
+int scf3_init(scf3_ctx** out, const scf3_geometry* geom, const scf_params* params,
+              const double* rhoA, const double* rhoB, void* dev_ws, size_t ws_bytes,
+              void* hip_stream);
+
+/* Advance nsteps >= 0 steps (two kernel launches each, asynchronous on the stream). */
+int scf3_step(scf3_ctx* ctx, int64_t nsteps);
+
+/* Observables of the current state; synchronises.  SCF_EUNSTABLE (with *out filled) when
+ * flags bit1 is set. */
+int scf3_observe(scf3_ctx* ctx, scf3_obs* out);
+
+/* Host copies of n_A, n_B (nz*ny*nx each, FP64, 0 on solid nodes).  Synchronises. */
+int scf3_get_density(scf3_ctx* ctx, double* nA, double* nB);
+
+/* Host copy of the populations f[k][i][z][y][x] (2*19*nz*ny*nx FP64; i = 0 rest, 1-6 axis
+ * +x,-x,+y,-y,+z,-z, 7-18 edges +x+y,-x-y,+x-y,-x+y,+x+z,-x-z,+x-z,-x+z,+y+z,-y-z,+y-z,-y+z;
+ * solid nodes 0).  Uses the idle population buffer as staging.  Synchronises. */
+int scf3_get_populations(scf3_ctx* ctx, double* f);
+
+int64_t scf3_time(const scf3_ctx* ctx);
+void scf3_destroy(scf3_ctx* ctx);
+
 #ifdef __cplusplus
 }
 #endif

@@ -58,6 +58,19 @@ class scf_sur_cfg(C.Structure):
                 ("eps", C.c_float), ("seed", C.c_uint64)]
 
 
+class scf3_geometry(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("x0", C.c_int32),
+                ("x1", C.c_int32), ("walls_y", C.c_int32), ("walls_z", C.c_int32)]
+
+
+class scf3_obs(C.Structure):
+    _fields_ = [("t", C.c_int64), ("mass", C.c_double * 2), ("z", C.c_double), ("flags", C.c_int32),
+                ("reserved", C.c_int32)]
+
+    def as_dict(self) -> dict:
+        return {"t": int(self.t), "mass": (self.mass[0], self.mass[1]), "z": self.z, "flags": int(self.flags)}
+
+
 class ScfError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"{ERROR_NAMES.get(code, code)}: {msg}")
@@ -115,6 +128,15 @@ _sig = {
     "scf_sur_train": (C.c_int, [_vp, C.c_int64, C.c_int32, _fp]),
     "scf_sur_predict": (C.c_int, [_vp, _fp, C.c_int64, _fp, C.POINTER(C.c_uint8)]),
     "scf_sur_destroy": (None, [_vp]),
+    "scf3_workspace_bytes": (C.c_size_t, [C.POINTER(scf3_geometry)]),
+    "scf3_init": (C.c_int, [C.POINTER(_vp), C.POINTER(scf3_geometry), C.POINTER(scf_params), _dp, _dp,
+                            _vp, C.c_size_t, _vp]),
+    "scf3_step": (C.c_int, [_vp, C.c_int64]),
+    "scf3_observe": (C.c_int, [_vp, C.POINTER(scf3_obs)]),
+    "scf3_get_density": (C.c_int, [_vp, _dp, _dp]),
+    "scf3_get_populations": (C.c_int, [_vp, _dp]),
+    "scf3_time": (C.c_int64, [_vp]),
+    "scf3_destroy": (None, [_vp]),
 }
 for _name, (_res, _args) in _sig.items():
     _f = getattr(lib, _name)

@@ -10,7 +10,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libscf.so")
 SOURCES = [os.path.join(CSRC, f) for f in ("scf_kernels.hip", "scf_runtime.hip", "sur_kernels.hip",
-                                          "sur_runtime.hip")]
+                                          "sur_runtime.hip", "scf3d_kernels.hip", "scf3d_runtime.hip")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 

@@ -215,3 +215,61 @@ class Batch:
         t = L.scf_tile()
         L.check(L.scf_batch_autotune(self._h, int(trial_steps), C.byref(t)))
         return t.as_dict()
+
+
+class Channel3:
+    """A three-dimensional (D3Q19) capillary: a slit (walls_y) or a square duct (walls_y and
+    walls_z) over x in [x0, x1) (scf3_init / scf3_step / scf3_observe).  Fields are (nz, ny, nx)."""
+
+    def __init__(self, nx: int, ny: int, nz: int, x0: int, x1: int, params: Params, rhoA: np.ndarray,
+                 rhoB: np.ndarray, walls_y: bool = True, walls_z: bool = False, device="cuda:0",
+                 stream: Optional[torch.cuda.Stream] = None):
+        self.shape = (int(nz), int(ny), int(nx))
+        self.params = params
+        self._g = L.scf3_geometry(int(nx), int(ny), int(nz), int(x0), int(x1), int(bool(walls_y)),
+                                  int(bool(walls_z)))
+        self._p = _params(params)
+        nbytes = L.scf3_workspace_bytes(C.byref(self._g))
+        if nbytes == 0:
+            raise L.ScfError(L.SCF_EINVAL, "invalid 3-D geometry")
+        self.ws = _workspace(nbytes, device)
+        a = np.ascontiguousarray(rhoA, dtype=np.float64)
+        b = np.ascontiguousarray(rhoB, dtype=np.float64)
+        if a.shape != self.shape or b.shape != self.shape:
+            raise ValueError("density fields must have shape (nz, ny, nx)")
+        h = C.c_void_p()
+        L.check(L.scf3_init(C.byref(h), C.byref(self._g), C.byref(self._p), _dptr(a), _dptr(b),
+                            C.c_void_p(self.ws.data_ptr()), nbytes, _stream_handle(stream)))
+        self._h = h
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) and getattr(L, "scf3_destroy", None) is not None:
+            L.scf3_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        self.close()
+
+    @property
+    def t(self) -> int:
+        return int(L.scf3_time(self._h))
+
+    def step(self, n: int = 1) -> "Channel3":
+        L.check(L.scf3_step(self._h, int(n)))
+        return self
+
+    def observe(self, allow_unstable: bool = False) -> dict:
+        o = L.scf3_obs()
+        L.check(L.scf3_observe(self._h, C.byref(o)), allow=(L.SCF_EUNSTABLE,) if allow_unstable else ())
+        return o.as_dict()
+
+    def density(self) -> Tuple[np.ndarray, np.ndarray]:
+        a = np.zeros(self.shape)
+        b = np.zeros(self.shape)
+        L.check(L.scf3_get_density(self._h, _dptr(a), _dptr(b)))
+        return a, b
+
+    def populations(self) -> np.ndarray:
+        f = np.zeros((2, 19) + self.shape)
+        L.check(L.scf3_get_populations(self._h, _dptr(f)))
+        return f

@@ -8,13 +8,14 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def _declared():
     text = open(os.path.join(ROOT, "include", "scf.h")).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(scf_[a-z_]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(scf3?_[a-z_]+)\s*\(", text)))
 
 
 def test_header_declares_the_calls():
     names = _declared()
     for n in ("scf_init", "scf_step", "scf_observe", "scf_batch_init", "scf_batch_step",
-              "scf_batch_observe", "scf_last_error", "scf_save", "scf_load"):
+              "scf_batch_observe", "scf_last_error", "scf_save", "scf_load", "scf3_init", "scf3_step",
+              "scf3_observe"):
         assert n in names
 
 
@@ -59,3 +60,23 @@ def test_init_rejects_bad_arguments_without_touching_the_device():
     assert L.scf_init(C.byref(h), C.byref(g), C.byref(p), dp(a), dp(a), C.c_void_p(256), 1 << 30,
                       None) == L.SCF_EINVAL
     assert b"tau" in L.scf_last_error()
+
+
+def test_3d_workspace_and_validation():
+    import ctypes as C
+    from paper_0807_0602_amd import _lib as L
+    g = L.scf3_geometry(64, 12, 10, 16, 48, 1, 1)
+    n = L.scf3_workspace_bytes(C.byref(g))
+    plane = 10 * 12 * 64
+    assert n >= 78 * plane * 4 and n % 256 == 0
+    assert L.scf3_workspace_bytes(C.byref(L.scf3_geometry(64, 2, 10, 16, 48, 1, 1))) == 0   # ny < 3
+    assert L.scf3_workspace_bytes(C.byref(L.scf3_geometry(64, 12, 10, 48, 16, 1, 1))) == 0  # x1 < x0
+    # alpha other than 4/9 is rejected before any device call
+    p = L.scf_params()
+    p.G = 0.9
+    for k in range(2):
+        p.tau[k] = 1.0; p.alpha[k] = 4.0 / 9.0; p.mass[k] = 1.0
+    p.alpha[1] = 0.6
+    h = C.c_void_p()
+    rc = L.scf3_init(C.byref(h), C.byref(g), C.byref(p), None, None, None, 0, None)
+    assert rc == L.SCF_EINVAL and b"alpha" in L.scf_last_error()
