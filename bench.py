@@ -251,6 +251,59 @@ def surrogate_gain(args) -> int:
     return 0
 
 
+def duct3d(args) -> int:
+    """MLUPS of the three-dimensional (D3Q19) duct capillary: 512 x 182 x 182 nodes (17.0 M),
+    walls on y and z over the middle half of x, two kernels per step."""
+    import numpy as np
+    import torch
+    from paper_0807_0602_amd import inputs
+    from paper_0807_0602_amd.scf import Channel3
+
+    nx, ny, nz, x0, x1 = 512, 182, 182, 128, 384
+    steps = args.steps if args.steps != 10000 else 1000
+    Z, Y, X = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    liq = X < x0
+    a = np.where(liq, 2.0, 0.06) + 1e-3 * inputs.uniform_pm1(1, 0, Y * nz + Z, X)
+    b = np.where(liq, 0.06, 2.0) + 1e-3 * inputs.uniform_pm1(1, 1, Y * nz + Z, X)
+    del Z, Y, X, liq
+    stream = torch.cuda.current_stream()
+    ch = Channel3(nx, ny, nz, x0, x1, inputs.Params(G=0.9, gw=(-0.2, 0.2)), a, b, walls_y=True, walls_z=True,
+                  stream=stream)
+    del a, b
+    ch.step(min(args.warmup, 50))
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    ch.step(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    obs = ch.observe(allow_unstable=True)
+    cells = nx * ny * nz
+    step_s = e0.elapsed_time(e1) / 1e3 / steps
+    # algorithmic bytes per node update of the two-kernel D3Q19 step: two pulls of 2 x 19 FP32
+    # populations (304 B), the density field written and read once (16 B), 152 B stored
+    bpl = 472
+    achieved = bpl * cells / step_s / 1e9
+    line = {
+        "metric": "D3Q19 binary-SC MLUPS (3-D duct capillary)", "value": round(cells * steps / wall / 1e6, 1),
+        "unit": "MLUPS", "n_gpus": 1, "steps": steps, "warmup": min(args.warmup, 50),
+        "ms_per_step": round(wall * 1e3 / steps, 5), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "duct3d_512x182x182", "nx": nx, "ny": ny, "nz": nz, "channel_x": [x0, x1],
+                   "G": 0.9, "gw": [-0.2, 0.2], "tau": [1.0, 1.0], "nodes": cells},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "k3_density + k3_collide", "bytes_per_node_update": bpl,
+                     "event_ms_per_step": round(step_s * 1e3, 5)},
+        "health": {"flags": obs["flags"], "z": obs["z"], "mass": list(obs["mass"])},
+    }
+    print(json.dumps(line), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -261,7 +314,7 @@ def main() -> int:
     ap.add_argument("--calibrate-copy", action="store_true")
     ap.add_argument("--tile", type=int, nargs="+", default=None, metavar="N",
                     help="BX CY ORDER [FUSE]: fixed schedule instead of the autotuner")
-    ap.add_argument("--workload", choices=["roofline", "sweep", "surrogate"], default="roofline")
+    ap.add_argument("--workload", choices=["roofline", "sweep", "surrogate", "duct3d"], default="roofline")
     ap.add_argument("--weights", default=os.path.join(ROOT, "paper_0807_0602_amd", "surrogate_weights_5in.npz"))
     ap.add_argument("--summarize-counters", nargs=4, default=None,
                     metavar=("FETCH_CSV", "WRITE_CSV", "FETCH_COPY_CSV", "WRITE_COPY_CSV"),
@@ -286,6 +339,8 @@ def main() -> int:
         return sweep(args)
     if args.workload == "surrogate":
         return surrogate_gain(args)
+    if args.workload == "duct3d":
+        return duct3d(args)
 
     from paper_0807_0602_amd import _lib as L
     from paper_0807_0602_amd import inputs
