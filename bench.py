@@ -11,7 +11,14 @@ once and written once).
 
 Prints ONE JSON line.  Options: --steps K (timed), --warmup W, --gpus N (only 1 is supported),
 --variant fused|two_kernel, --no-cpu-baseline, --calibrate-copy (runs only a plain copy kernel,
-for counter calibration under rocprofv3), --tile BX CY ORDER (skip the autotuner).
+for counter calibration under rocprofv3), --tile BX CY ORDER [FUSE] (skip the autotuner; FUSE 2
+runs two time steps per launch).  With two steps per launch the roofline's `achieved` stays in
+the metric's unit, 144 bytes per node update (the bytes a single step moves), and `traffic`
+gives the measured bytes per launch.
+
+Further workloads (--workload): small (the 200 x 24 parity capillary, microseconds per step for
+direct and graph launches and the oracle on the whole run), washburn (MLUPS on the 4096 x 202
+capillary), duct3d (MLUPS of the 3-D D3Q19 duct, 512 x 182 x 182).
 
 --workload surrogate measures the learned surrogate against the batched LBM on 64 fresh
 channels drawn like its training set (seed 3): the LBM simulates them (points/hour of the LBM)
@@ -138,10 +145,32 @@ def cpu_baseline(case, budget_s: float = 12.0, max_steps: int = 40) -> dict:
         steps += 1
     dt = time.perf_counter() - t0
     cells = case.geom.nx * case.geom.ny
-    return {"value": round(cells * steps / dt / 1e6, 3), "unit": "MLUPS", "cores": oracle.lib().orc_threads(),
+    cores = oracle.lib().orc_threads()
+    # one thread, two steps, for the single-core rate
+    oracle.set_threads(1)
+    t1 = time.perf_counter()
+    o.step(2)
+    dt1 = time.perf_counter() - t1
+    oracle.set_threads(threads)
+    return {"value": round(cells * steps / dt / 1e6, 3), "unit": "MLUPS", "cores": cores,
             "kind": "oracle",
             "sample": f"{steps} whole-box FP64 steps of the {case.geom.nx}x{case.geom.ny} capillary "
-                      f"({cells * steps / 1e6:.0f} M node updates, {dt:.1f} s)"}
+                      f"({cells * steps / 1e6:.0f} M node updates, {dt:.1f} s)",
+            "single_thread_mlups": round(2 * cells / dt1 / 1e6, 3),
+            "host": _host_cpu()}
+
+
+def _host_cpu() -> dict:
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"model": model, "nproc": os.cpu_count()}
 
 
 def calibrate_copy(nbytes: int = 1 << 30, reps: int = 5) -> None:
@@ -304,6 +333,82 @@ def duct3d(args) -> int:
     return 0
 
 
+def small(args) -> int:
+    """The 200 x 24 parity capillary (4 800 nodes): launch-latency bound, so microseconds per step
+    for direct launches and for captured graphs, one and two steps per launch, and the FP64
+    oracle on the whole 2000-step run."""
+    import torch
+    import oracle
+    from paper_0807_0602_amd import inputs
+    from paper_0807_0602_amd.scf import Channel
+
+    case = inputs.capillary_small(seed=1)
+    steps = 2000
+    out = {}
+    stream = torch.cuda.current_stream()
+    probe = Channel.from_case(case, stream=stream)
+    tuned = probe.autotune(50)
+    probe.close()
+    out["schedule"] = tuned
+    for fuse in (1, 2):
+        for gs, name in ((0, "eager"), (200, "graph")):
+            ch = Channel.from_case(case, stream=stream)
+            ch.set_tile(tuned["bx"], tuned["cy"], gs, tuned["order"], fuse)
+            ch.step(200)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ch.step(steps)
+            torch.cuda.synchronize()
+            out[f"{name}_fuse{fuse}_us_per_step"] = round((time.perf_counter() - t0) * 1e6 / steps, 2)
+            ch.close()
+    oracle.set_threads(1)
+    o = oracle.Oracle.from_case(case).init(*case.fields())
+    t0 = time.perf_counter()
+    o.step(steps)
+    dto = time.perf_counter() - t0
+    cells = case.geom.nx * case.geom.ny
+    best = min(v for k, v in out.items() if k.endswith("_us_per_step"))
+    line = {"metric": "microseconds per step, 200 x 24 capillary (launch-latency bound)", "value": best,
+            "unit": "us/step", "n_gpus": 1, "steps": steps, "warmup": 200, "ms_per_step": best / 1e3,
+            "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+            "data": "synthetic", "config": {"workload": "capillary_200x24", "nodes": cells, **out},
+            "cpu_baseline": {"value": round(cells * steps / dto / 1e6, 3), "unit": "MLUPS", "cores": 1,
+                             "kind": "oracle", "sample": f"the whole 2000-step run ({dto:.2f} s)"}}
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+def washburn(args) -> int:
+    """MLUPS on the 4096 x 202 Washburn capillary (H = 200, capillary length 3072), autotuned."""
+    import torch
+    from paper_0807_0602_amd import inputs
+    from paper_0807_0602_amd.scf import Channel
+
+    case = inputs.with_params(inputs.capillary_washburn(seed=1), tau=(1.25, 1.0))
+    steps = args.steps if args.steps != 10000 else 20000
+    stream = torch.cuda.current_stream()
+    ch = Channel.from_case(case, stream=stream)
+    ch.autotune(20)
+    tile = ch.tile()
+    ch.step(min(args.warmup, 200))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ch.step(steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    obs = ch.observe(allow_unstable=True)
+    cells = case.geom.nx * case.geom.ny
+    line = {"metric": "D2Q9 binary-SC MLUPS (Washburn capillary)", "value": round(cells * steps / wall / 1e6, 1),
+            "unit": "MLUPS", "n_gpus": 1, "steps": steps, "warmup": min(args.warmup, 200),
+            "ms_per_step": round(wall * 1e3 / steps, 5), "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": case.name, "nx": case.geom.nx, "ny": case.geom.ny, "tau": list(case.params.tau),
+                       "gw": list(case.params.gw), "schedule": tile, "nodes": cells},
+            "health": {"flags": obs["flags"], "z": obs["z"]}}
+    print(json.dumps(line), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -314,7 +419,8 @@ def main() -> int:
     ap.add_argument("--calibrate-copy", action="store_true")
     ap.add_argument("--tile", type=int, nargs="+", default=None, metavar="N",
                     help="BX CY ORDER [FUSE]: fixed schedule instead of the autotuner")
-    ap.add_argument("--workload", choices=["roofline", "sweep", "surrogate", "duct3d"], default="roofline")
+    ap.add_argument("--workload", choices=["roofline", "sweep", "surrogate", "duct3d", "small", "washburn"],
+                    default="roofline")
     ap.add_argument("--weights", default=os.path.join(ROOT, "paper_0807_0602_amd", "surrogate_weights_5in.npz"))
     ap.add_argument("--summarize-counters", nargs=4, default=None,
                     metavar=("FETCH_CSV", "WRITE_CSV", "FETCH_COPY_CSV", "WRITE_COPY_CSV"),
@@ -341,6 +447,10 @@ def main() -> int:
         return surrogate_gain(args)
     if args.workload == "duct3d":
         return duct3d(args)
+    if args.workload == "small":
+        return small(args)
+    if args.workload == "washburn":
+        return washburn(args)
 
     from paper_0807_0602_amd import _lib as L
     from paper_0807_0602_amd import inputs
