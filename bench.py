@@ -282,7 +282,8 @@ def surrogate_gain(args) -> int:
 
 def duct3d(args) -> int:
     """MLUPS of the three-dimensional (D3Q19) duct capillary: 512 x 182 x 182 nodes (17.0 M),
-    walls on y and z over the middle half of x, two kernels per step."""
+    walls on y and z over the middle half of x; the fused one-kernel step by default (--cy3 rows
+    of y per tile), the two-kernel step with --cy3 0."""
     import numpy as np
     import torch
     from paper_0807_0602_amd import inputs
@@ -299,6 +300,8 @@ def duct3d(args) -> int:
     ch = Channel3(nx, ny, nz, x0, x1, inputs.Params(G=0.9, gw=(-0.2, 0.2)), a, b, walls_y=True, walls_z=True,
                   stream=stream)
     del a, b
+    fused = args.cy3 > 0
+    ch.set_schedule(fused=fused, cy=max(args.cy3, 1))
     ch.step(min(args.warmup, 50))
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
@@ -312,9 +315,10 @@ def duct3d(args) -> int:
     obs = ch.observe(allow_unstable=True)
     cells = nx * ny * nz
     step_s = e0.elapsed_time(e1) / 1e3 / steps
-    # algorithmic bytes per node update of the two-kernel D3Q19 step: two pulls of 2 x 19 FP32
-    # populations (304 B), the density field written and read once (16 B), 152 B stored
-    bpl = 472
+    # algorithmic bytes per node update: the fused step pulls 2 x 19 FP32 populations once
+    # (152 B) and stores as many (152 B); the two-kernel step pulls twice (304 B), writes and
+    # reads the density field once (16 B) and stores 152 B
+    bpl = 304 if fused else 472
     achieved = bpl * cells / step_s / 1e9
     line = {
         "metric": "D3Q19 binary-SC MLUPS (3-D duct capillary)", "value": round(cells * steps / wall / 1e6, 1),
@@ -325,7 +329,8 @@ def duct3d(args) -> int:
                    "G": 0.9, "gw": [-0.2, 0.2], "tau": [1.0, 1.0], "nodes": cells},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": "k3_density + k3_collide", "bytes_per_node_update": bpl,
+                     "kernel": ("k3_fused, %d rows of y per 64 x 4 tile" % ch.schedule()["cy"]) if fused
+                     else "k3_density + k3_collide", "bytes_per_node_update": bpl,
                      "event_ms_per_step": round(step_s * 1e3, 5)},
         "health": {"flags": obs["flags"], "z": obs["z"], "mass": list(obs["mass"])},
     }
@@ -421,6 +426,8 @@ def main() -> int:
                     help="BX CY ORDER [FUSE]: fixed schedule instead of the autotuner")
     ap.add_argument("--workload", choices=["roofline", "sweep", "surrogate", "duct3d", "small", "washburn"],
                     default="roofline")
+    ap.add_argument("--cy3", type=int, default=16,
+                    help="duct3d: rows of y per tile of the fused 3-D step; 0 = the two-kernel step")
     ap.add_argument("--weights", default=os.path.join(ROOT, "paper_0807_0602_amd", "surrogate_weights_5in.npz"))
     ap.add_argument("--summarize-counters", nargs=4, default=None,
                     metavar=("FETCH_CSV", "WRITE_CSV", "FETCH_COPY_CSV", "WRITE_COPY_CSV"),

@@ -287,7 +287,10 @@ void scf_sur_destroy(scf_sur* s);
  * (12 edge links); bulk and wall forces of eqs. forcing and forcingw with the same link weights;
  * common velocity, shifted equilibrium, BGK, pull streaming with half-way bounce-back.  The
  * weights' z-projection is D2Q9 with rest fraction 4/9, so a z-independent state evolves as the
- * 2-D model.  Two kernels per step (densities, then pull + collide), FP32 state.
+ * 2-D model.  FP32 state.  By default one fused kernel per step: tiles of 64 x 4 (x, z) nodes walk
+ * cy rows of y, keeping the densities of three y-slices in LDS; the two-kernel form (a density
+ * field, then pull + collide) is selectable (scf3_set_schedule) and is the only one when one
+ * component's 19 planes exceed 2 GiB (32-bit buffer offsets).  Both give identical results.
  * ------------------------------------------------------------------------------------------- */
 
 typedef struct {
@@ -322,8 +325,17 @@ int scf3_init(scf3_ctx** out, const scf3_geometry* geom, const scf_params* param
               const double* rhoA, const double* rhoB, void* dev_ws, size_t ws_bytes,
               void* hip_stream);
 
-/* Advance nsteps >= 0 steps (two kernel launches each, asynchronous on the stream). */
+/* Advance nsteps >= 0 steps (one launch each, two in the two-kernel form; asynchronous on the
+ * stream). */
 int scf3_step(scf3_ctx* ctx, int64_t nsteps);
+
+/* Step schedule: fused = 1 (one kernel, cy >= 1 rows of y per tile, default 16 or the two-kernel
+ * form where the fused one does not fit) or fused = 0 (two kernels, cy ignored).  The state is
+ * unchanged; results do not depend on the schedule.  *_get_* writes the current one.
+ * Errors: SCF_EINVAL (fused not 0/1, cy < 1, or fused = 1 where a component's 19 planes exceed
+ * 2 GiB). */
+int scf3_set_schedule(scf3_ctx* ctx, int32_t fused, int32_t cy);
+int scf3_get_schedule(const scf3_ctx* ctx, int32_t* fused, int32_t* cy);
 
 /* Observables of the current state; synchronises.  SCF_EUNSTABLE (with *out filled) when
  * flags bit1 is set. */

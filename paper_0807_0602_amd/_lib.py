@@ -132,6 +132,8 @@ _sig = {
     "scf3_init": (C.c_int, [C.POINTER(_vp), C.POINTER(scf3_geometry), C.POINTER(scf_params), _dp, _dp,
                             _vp, C.c_size_t, _vp]),
     "scf3_step": (C.c_int, [_vp, C.c_int64]),
+    "scf3_set_schedule": (C.c_int, [_vp, C.c_int32, C.c_int32]),
+    "scf3_get_schedule": (C.c_int, [_vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
     "scf3_observe": (C.c_int, [_vp, C.POINTER(scf3_obs)]),
     "scf3_get_density": (C.c_int, [_vp, _dp, _dp]),
     "scf3_get_populations": (C.c_int, [_vp, _dp]),

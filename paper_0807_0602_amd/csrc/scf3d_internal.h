@@ -40,6 +40,8 @@ struct Obs3 {
 // `h` is the host copy of the device table entry `c` (launch geometry).
 hipError_t launch_init(const Chan3& h, const Chan3* c, float* ws, hipStream_t s);
 hipError_t launch_step(const Chan3& h, const Chan3* c, float* ws, int src, hipStream_t s);
+// One fused launch per step: 64 x 4 (x, z) tiles walking `cy` rows of y.
+hipError_t launch_step_fused(const Chan3& h, const Chan3* c, float* ws, int src, int cy, hipStream_t s);
 hipError_t launch_observe(const Chan3& h, const Chan3* c, float* ws, int src, Part3* parts, Obs3* out,
                           hipStream_t s);
 hipError_t launch_pull_out(const Chan3& h, const Chan3* c, float* ws, int src, hipStream_t s);

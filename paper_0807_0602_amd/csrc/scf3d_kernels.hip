@@ -6,8 +6,8 @@
 // pull streaming with half-way bounce-back.  The z-projection of these weights is D2Q9 with rest
 // fraction 4/9, so z-independent states follow the 2-D model.
 //
-// Two kernels per step: (1) pulled densities of every node into a density field, (2) pull,
-// neighbour densities from the field, collision, store into the other population buffer.
+// The fused step (k3_fused) walks y-slices of x-z tiles with the densities in an LDS ring; the
+// two-kernel variant (k3_density, k3_collide) writes a density field and reads it back.
 // Storage: FP32, f[k][i][z][y][pitch], x fastest, pitch = nx rounded up to 64.
 #include "scf3d_internal.h"
 
@@ -155,6 +155,182 @@ k3_collide(const Chan3* __restrict__ cp, float* __restrict__ ws, int src) {
           __builtin_fmaf(c.tm[0], aA[2], U[2]), c.omega[0], d, c.plane, at);
     relax(f + 19, nB, __builtin_fmaf(c.tm[1], aB[0], U[0]), __builtin_fmaf(c.tm[1], aB[1], U[1]),
           __builtin_fmaf(c.tm[1], aB[2], U[2]), c.omega[1], d + 19 * c.plane, c.plane, at);
+}
+
+// ---------------------------------------------------------------------------------------------
+// Fused 3-D step.  A block of BX x BZ threads owns the columns x in [xb, xb + BX), z in
+// [zb, zb + BZ) and walks rows y upward through [yb, ye).  Iteration `it` pulls one y-slice of
+// the tile plus its one-node halo ring in x and z (the ring's nodes are pulled by the first
+// 2 (BX + 2) + 2 BZ threads), writes the slice's densities into a 4-slot LDS ring, and after
+// one barrier collides the previous slice, whose populations were kept in registers: all 18
+// neighbour densities of a node come from three ring slots.  The first and last slices pulled
+// are density-only halos.  A slot written at iteration it+1 was last read by the collision of
+// iteration it-1, finished by every thread before the barrier of iteration it.
+// ---------------------------------------------------------------------------------------------
+__device__ __forceinline__ bool in_x(const Chan3& c, int x) { return (unsigned)(x - c.x0) < (unsigned)(c.x1 - c.x0); }
+
+// True if a solid node may lie among (x, y, z) and its 18 neighbours (periodic in x).
+__device__ __forceinline__ bool near_solid(const Chan3& c, int x, int y, int z) {
+    if (!in_x(c, wrapc(x - 1, c.nx)) && !in_x(c, x) && !in_x(c, wrapc(x + 1, c.nx))) return false;
+    return (c.walls_y && (y <= 1 || y >= c.ny - 2)) || (c.walls_z && (z <= 1 || z >= c.nz - 2));
+}
+
+// Buffer-descriptor access for the fused step: one descriptor per component of the source buffer
+// (19 planes, below 2 GiB, checked by the host), 32-bit byte offsets, plane offsets in scalar
+// registers.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const float* base, int64_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(base), 0, (int)bytes, 0x00020000);
+}
+__device__ __forceinline__ float bload(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0));
+}
+
+__device__ __forceinline__ unsigned idx32(const Chan3& c, int x, int y, int z) {
+    return ((unsigned)z * (unsigned)c.ny + (unsigned)y) * (unsigned)c.pitch + (unsigned)x;
+}
+
+// As pull, through the descriptors rA, rB of the two components (Pb = plane bytes); WALLS adds
+// the bounce-back tests.
+template <bool WALLS>
+__device__ __forceinline__ void pull_buf(__amdgpu_buffer_rsrc_t rA, __amdgpu_buffer_rsrc_t rB, unsigned Pb,
+                                         const Chan3& c, int x, int y, int z, float f[38]) {
+    const unsigned own = idx32(c, x, y, z) * 4u;
+#pragma unroll
+    for (int i = 0; i < 19; ++i) {
+        const int xs = wrapc(x - kCX[i], c.nx), ys = wrapc(y - kCY[i], c.ny), zs = wrapc(z - kCZ[i], c.nz);
+        const unsigned off = idx32(c, xs, ys, zs) * 4u;
+        if (WALLS && i > 0) {
+            // bounce-back lanes read their own node's opposite direction: the plane goes into the
+            // per-lane offset so the scalar offset stays uniform
+            const unsigned o = solid(c, xs, ys, zs) ? own + (unsigned)kOpp[i] * Pb : off + (unsigned)i * Pb;
+            f[i] = bload(rA, o, 0u);
+            f[19 + i] = bload(rB, o, 0u);
+        } else {
+            f[i] = bload(rA, off, (unsigned)i * Pb);
+            f[19 + i] = bload(rB, off, (unsigned)i * Pb);
+        }
+    }
+}
+
+__device__ __forceinline__ void pull_any(__amdgpu_buffer_rsrc_t rA, __amdgpu_buffer_rsrc_t rB, unsigned Pb,
+                                         const Chan3& c, int x, int y, int z, float f[38]) {
+    if (near_solid(c, x, y, z))
+        pull_buf<true>(rA, rB, Pb, c, x, y, z, f);
+    else
+        pull_buf<false>(rA, rB, Pb, c, x, y, z, f);
+}
+
+template <int BX, int BZ>
+__global__ void __launch_bounds__(BX * BZ)
+k3_fused(const Chan3* __restrict__ cp, float* __restrict__ ws, int src, int cy) {
+    constexpr int SX = BX + 2, SZ = BZ + 2;
+    constexpr int NH = 2 * SX + 2 * BZ;   // halo ring of the x-z tile
+    __shared__ float sn[2][4][SZ][SX];
+    const Chan3 c = *cp;
+    const int tid = threadIdx.x;
+    const int tx = tid % BX, tz = tid / BX;
+    const int xb = blockIdx.x * BX, zb = blockIdx.y * BZ;
+    const int yb = blockIdx.z * cy, ye = min(yb + cy, c.ny);
+    // Tile columns past the edge of the box hold the periodic images of nodes (as many times over
+    // as needed when the box is narrower than the tile), so the LDS neighbours of every active
+    // column are the true periodic neighbours; only active threads collide and store.
+    const bool act = xb + tx < c.nx && zb + tz < c.nz;
+    const int x = (xb + tx) % c.nx, z = (zb + tz) % c.nz;
+    // halo node of this thread (ring position h = tid), in tile coordinates (hx, hz) in [0, SX) x [0, SZ)
+    int hx = 0, hz = 0;
+    if (tid < SX) {
+        hx = tid; hz = 0;
+    } else if (tid < 2 * SX) {
+        hx = tid - SX; hz = SZ - 1;
+    } else if (tid < 2 * SX + BZ) {
+        hx = 0; hz = 1 + tid - 2 * SX;
+    } else {
+        hx = SX - 1; hz = 1 + tid - 2 * SX - BZ;
+    }
+    const int gx = (xb - 1 + hx + c.nx) % c.nx, gz = (zb - 1 + hz + c.nz) % c.nz;
+    const bool halo = tid < NH;
+    const int64_t comp_bytes = (int64_t)19 * c.plane * 4;
+    const float* gsrc = ws + c.off + (int64_t)src * 38 * c.plane;
+    const __amdgpu_buffer_rsrc_t rA = make_rsrc(gsrc, comp_bytes);
+    const __amdgpu_buffer_rsrc_t rB = make_rsrc(gsrc + 19 * c.plane, comp_bytes);
+    const unsigned Pb = (unsigned)(c.plane * 4);
+    float* __restrict__ d = ws + c.off + (int64_t)(src ^ 1) * 38 * c.plane;
+    float q[38];
+#pragma unroll
+    for (int i = 0; i < 38; ++i) q[i] = 0.0f;
+    float qA = 0.0f, qB = 0.0f;
+    int y = wrapc(yb - 1, c.ny);
+    const int niter = ye - yb + 2;
+    for (int it = 0; it < niter; ++it) {
+        const int slot = it & 3;
+        // the halo ring first, so that its registers are free again before the slice's own pull
+        if (halo) {
+            float h[38];
+            float hA = 0.0f, hB = 0.0f;
+            if (!solid(c, gx, y, gz)) {
+                pull_any(rA, rB, Pb, c, gx, y, gz, h);
+                hA = sum19(h);
+                hB = sum19(h + 19);
+            }
+            sn[0][slot][hz][hx] = hA;
+            sn[1][slot][hz][hx] = hB;
+        }
+        float p[38];
+        float nA = 0.0f, nB = 0.0f;
+        const bool sol = solid(c, x, y, z);
+        pull_any(rA, rB, Pb, c, x, y, z, p);
+        if (!sol) {
+            nA = sum19(p);
+            nB = sum19(p + 19);
+        }
+        sn[0][slot][tz + 1][tx + 1] = nA;
+        sn[1][slot][tz + 1][tx + 1] = nB;
+        __syncthreads();
+        const int yc = y == 0 ? c.ny - 1 : y - 1;   // the slice pulled one iteration ago
+        if (it >= 2 && act && !solid(c, x, yc, z)) {
+            const int sy[3] = {(it - 2) & 3, (it - 1) & 3, slot};   // slices yc - 1, yc, yc + 1
+            float jA[3] = {0.0f, 0.0f, 0.0f}, jB[3] = {0.0f, 0.0f, 0.0f};
+            float sA[3] = {0.0f, 0.0f, 0.0f}, sB[3] = {0.0f, 0.0f, 0.0f}, sw[3] = {0.0f, 0.0f, 0.0f};
+            const bool nw = near_solid(c, x, yc, z);
+#pragma unroll
+            for (int i = 1; i < 19; ++i) {
+                const float cx = (float)kCX[i], cyf = (float)kCY[i], cz = (float)kCZ[i];
+                jA[0] += cx * q[i]; jA[1] += cyf * q[i]; jA[2] += cz * q[i];
+                jB[0] += cx * q[19 + i]; jB[1] += cyf * q[19 + i]; jB[2] += cz * q[19 + i];
+                const int s = sy[kCY[i] + 1];
+                const float w = i < 7 ? kWA : kWE;
+                const float a = w * sn[0][s][tz + 1 + kCZ[i]][tx + 1 + kCX[i]];
+                const float b = w * sn[1][s][tz + 1 + kCZ[i]][tx + 1 + kCX[i]];
+                sA[0] += a * cx; sA[1] += a * cyf; sA[2] += a * cz;
+                sB[0] += b * cx; sB[1] += b * cyf; sB[2] += b * cz;
+                if (nw) {
+                    const float so = solid(c, wrapc(x + kCX[i], c.nx), wrapc(yc + kCY[i], c.ny),
+                                           wrapc(z + kCZ[i], c.nz)) ? w : 0.0f;
+                    sw[0] += so * cx; sw[1] += so * cyf; sw[2] += so * cz;
+                }
+            }
+            float aA[3], aB[3];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                aA[k] = __builtin_fmaf(-c.G, sB[k], -(c.gw[0] * sw[k]));
+                aB[k] = __builtin_fmaf(-c.G, sA[k], -(c.gw[1] * sw[k]));
+            }
+            const float inv = 1.0f / __builtin_fmaf(c.wm[0], qA, c.wm[1] * qB);
+            float U[3];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) U[k] = __builtin_fmaf(c.wm[0], jA[k], c.wm[1] * jB[k]) * inv;
+            const int64_t at = idx(c, x, yc, z);
+            relax(q, qA, __builtin_fmaf(c.tm[0], aA[0], U[0]), __builtin_fmaf(c.tm[0], aA[1], U[1]),
+                  __builtin_fmaf(c.tm[0], aA[2], U[2]), c.omega[0], d, c.plane, at);
+            relax(q + 19, qB, __builtin_fmaf(c.tm[1], aB[0], U[0]), __builtin_fmaf(c.tm[1], aB[1], U[1]),
+                  __builtin_fmaf(c.tm[1], aB[2], U[2]), c.omega[1], d + 19 * c.plane, c.plane, at);
+        }
+#pragma unroll
+        for (int i = 0; i < 38; ++i) q[i] = p[i];
+        qA = nA;
+        qB = nB;
+        y = y == c.ny - 1 ? 0 : y + 1;
+    }
 }
 
 // Initial state: the resident buffer holds the populations whose pull is the rest equilibrium
@@ -315,6 +491,14 @@ hipError_t launch_step(const Chan3& h, const Chan3* c, float* ws, int src, hipSt
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k3_collide, grid_of(h), dim3(kThreads), 0, s, c, ws, src);
+    return hipGetLastError();
+}
+
+hipError_t launch_step_fused(const Chan3& h, const Chan3* c, float* ws, int src, int cy, hipStream_t s) {
+    constexpr int BX = 64, BZ = 4;
+    cy = cy < 1 ? 1 : (cy > h.ny ? h.ny : cy);
+    const dim3 grid((h.nx + BX - 1) / BX, (h.nz + BZ - 1) / BZ, (h.ny + cy - 1) / cy);
+    hipLaunchKernelGGL((k3_fused<BX, BZ>), grid, dim3(BX * BZ), 0, s, c, ws, src, cy);
     return hipGetLastError();
 }
 

@@ -2,6 +2,7 @@
 // the 2-D library it allocates no device memory: it carves the caller's workspace.
 #include <hip/hip_runtime.h>
 
+#include <climits>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -41,6 +42,9 @@ bool geom_ok(const scf3_geometry* g, std::string* why) {
 
 int pitch_of(int nx) { return (nx + 63) / 64 * 64; }
 
+// The fused kernel addresses one component's 19 planes with 32-bit buffer offsets.
+bool fused_fits(int64_t plane) { return (int64_t)19 * plane * (int64_t)sizeof(float) <= INT32_MAX; }
+
 Plan3 plan(const scf3_geometry& g) {
     Plan3 p;
     size_t off = 0;
@@ -65,6 +69,7 @@ struct scf3_ctx {
     hipStream_t stream = nullptr;
     int cur = 0;
     int64_t t = 0;
+    int fused = 1, cy = 16;
     float* base() const { return reinterpret_cast<float*>(ws); }
     scf3::Chan3* d_chan() const { return reinterpret_cast<scf3::Chan3*>(ws + lay.chan); }
 };
@@ -110,6 +115,7 @@ int scf3_init(scf3_ctx** out, const scf3_geometry* geom, const scf_params* p, co
     h.x0 = geom->x0; h.x1 = geom->x1; h.walls_y = geom->walls_y ? 1 : 0; h.walls_z = geom->walls_z ? 1 : 0;
     h.off = (int64_t)(lay.pop / sizeof(float));
     h.plane = (int64_t)geom->nz * geom->ny * h.pitch;
+    c->fused = fused_fits(h.plane) ? 1 : 0;
     h.G = (float)p->G;
     for (int k = 0; k < 2; ++k) {
         h.gw[k] = (float)p->gw[k];
@@ -135,10 +141,31 @@ int scf3_init(scf3_ctx** out, const scf3_geometry* geom, const scf_params* p, co
 int scf3_step(scf3_ctx* c, int64_t nsteps) {
     if (!c || nsteps < 0) return fail(SCF_EINVAL, "bad context or negative step count");
     for (int64_t i = 0; i < nsteps; ++i) {
-        HIP_TRY3(scf3::launch_step(c->chan, c->d_chan(), c->base(), c->cur, c->stream));
+        if (c->fused)
+            HIP_TRY3(scf3::launch_step_fused(c->chan, c->d_chan(), c->base(), c->cur, c->cy, c->stream));
+        else
+            HIP_TRY3(scf3::launch_step(c->chan, c->d_chan(), c->base(), c->cur, c->stream));
         c->cur ^= 1;
         c->t += 1;
     }
+    return SCF_OK;
+}
+
+int scf3_set_schedule(scf3_ctx* c, int32_t fused, int32_t cy) {
+    if (!c) return fail(SCF_EINVAL, "context is NULL");
+    if (fused != 0 && fused != 1) return fail(SCF_EINVAL, "fused must be 0 or 1");
+    if (fused && cy < 1) return fail(SCF_EINVAL, "cy must be >= 1");
+    if (fused && !fused_fits(c->chan.plane))
+        return fail(SCF_EINVAL, "box too large for the fused kernel (19 planes above 2 GiB)");
+    c->fused = fused;
+    if (fused) c->cy = cy;
+    return SCF_OK;
+}
+
+int scf3_get_schedule(const scf3_ctx* c, int32_t* fused, int32_t* cy) {
+    if (!c || !fused || !cy) return fail(SCF_EINVAL, "NULL argument");
+    *fused = c->fused;
+    *cy = c->cy;
     return SCF_OK;
 }
 

@@ -258,6 +258,16 @@ class Channel3:
         L.check(L.scf3_step(self._h, int(n)))
         return self
 
+    def set_schedule(self, fused: bool = True, cy: int = 16) -> "Channel3":
+        """One fused kernel per step walking cy rows of y per tile, or the two-kernel form."""
+        L.check(L.scf3_set_schedule(self._h, int(fused), int(cy)))
+        return self
+
+    def schedule(self) -> dict:
+        f, cy = C.c_int32(), C.c_int32()
+        L.check(L.scf3_get_schedule(self._h, C.byref(f), C.byref(cy)))
+        return {"fused": bool(f.value), "cy": int(cy.value)}
+
     def observe(self, allow_unstable: bool = False) -> dict:
         o = L.scf3_obs()
         L.check(L.scf3_observe(self._h, C.byref(o)), allow=(L.SCF_EUNSTABLE,) if allow_unstable else ())

@@ -80,3 +80,4 @@ def test_3d_workspace_and_validation():
     h = C.c_void_p()
     rc = L.scf3_init(C.byref(h), C.byref(g), C.byref(p), None, None, None, 0, None)
     assert rc == L.SCF_EINVAL and b"alpha" in L.scf_last_error()
+    assert L.scf3_set_schedule(None, 1, 16) == L.SCF_EINVAL

@@ -1,7 +1,9 @@
 """GPU parity of the three-dimensional (D3Q19) capillary against the FP64 3-D oracle, on the same
 seeded inputs: populations after a few steps within FP32 rounding, densities within 1e-5 after
 300 steps, front within 0.5 lattice units, mass within 1e-5; a z-independent slit equals the
-2-D GPU channel to FP32 rounding; and a wetting duct fills.
+2-D GPU channel to FP32 rounding; and a wetting duct fills.  The fused one-kernel step (the
+default) equals the two-kernel step bit for bit for every row count per tile, on boxes narrower
+than a tile, with ragged tiles and with the capillary touching the periodic x edge.
 """
 import sys
 
@@ -116,3 +118,50 @@ def test_wetting_duct_fills(S):
         z.append(o["z"])
     _say(f"  duct front every 1000 steps: {np.round(z, 2).tolist()}")
     assert z[-1] > z[0] + 3.0 and np.all(np.diff(z[2:]) > 0)
+
+
+SCHED_GEOMS = [
+    ("duct_ragged", dict(nx=70, ny=11, nz=7, x0=9, x1=61, walls_y=True, walls_z=True), (-0.25, 0.1), (1.2, 0.9)),
+    ("wall_to_edge", dict(nx=66, ny=9, nz=6, x0=0, x1=66, walls_y=True, walls_z=True), (-0.2, 0.2), (1.0, 0.8)),
+    ("edge_x1", dict(nx=40, ny=8, nz=5, x0=25, x1=40, walls_y=True, walls_z=False), (0.1, -0.1), (0.9, 1.4)),
+    ("edge_x0", dict(nx=40, ny=8, nz=5, x0=0, x1=17, walls_y=False, walls_z=True), (-0.3, 0.0), (1.0, 1.0)),
+    ("tiny", dict(nx=3, ny=3, nz=3, x0=1, x1=2, walls_y=True, walls_z=False), (-0.2, 0.2), (1.0, 1.0)),
+    ("open", dict(nx=33, ny=9, nz=7, x0=0, x1=0, walls_y=False, walls_z=False), (0.0, 0.0), (1.0, 0.8)),
+]
+
+
+@pytest.mark.parametrize("name,g,gw,tau", SCHED_GEOMS, ids=[x[0] for x in SCHED_GEOMS])
+def test_fused_equals_two_kernel_step(S, name, g, gw, tau):
+    ref, _ = _pair(S, g, gw, tau)
+    ref.set_schedule(fused=False)
+    assert ref.schedule()["fused"] is False
+    ref.step(23)
+    want = ref.populations()
+    for cy in (1, 2, 5, 16, 1 << 30):
+        _say(f"case: 3-D fused {name} cy={cy}, 23 steps")
+        ch, _ = _pair(S, g, gw, tau)
+        ch.set_schedule(fused=True, cy=cy)
+        ch.step(23)
+        assert np.array_equal(ch.populations(), want), cy
+
+
+def test_fused_oracle_parity_on_a_ragged_duct(S):
+    name, g, gw, tau = SCHED_GEOMS[0]
+    ch, o = _pair(S, g, gw, tau)
+    assert ch.schedule() == {"fused": True, "cy": 16}
+    ch.set_schedule(fused=True, cy=4)
+    ch.step(40)
+    o.step(40)
+    err = np.abs(ch.populations() - o.populations()).max()
+    _say(f"  fused ragged duct vs oracle after 40 steps: max|df| = {err:.2e}")
+    assert err <= 2e-6
+
+
+def test_schedule_rejects_bad_values(S):
+    from paper_0807_0602_amd import _lib as L
+    name, g, gw, tau = GEOMS[1]
+    ch, _ = _pair(S, g, gw, tau)
+    for bad in ((2, 8), (1, 0), (-1, 4)):
+        with pytest.raises(L.ScfError):
+            ch.set_schedule(*bad)
+    assert ch.schedule() == {"fused": True, "cy": 16}
