@@ -225,12 +225,20 @@ __global__ void __launch_bounds__(BX * BZ)
 k3_fused(const Chan3* __restrict__ cp, float* __restrict__ ws, int src, int cy) {
     constexpr int SX = BX + 2, SZ = BZ + 2;
     constexpr int NH = 2 * SX + 2 * BZ;   // halo ring of the x-z tile
+    static_assert(NH <= BX * BZ, "one thread per halo node");
     __shared__ float sn[2][4][SZ][SX];
     const Chan3 c = *cp;
     const int tid = threadIdx.x;
     const int tx = tid % BX, tz = tid / BX;
-    const int xb = blockIdx.x * BX, zb = blockIdx.y * BZ;
-    const int yb = blockIdx.z * cy, ye = min(yb + cy, c.ny);
+    // Workgroups are dispatched to the eight XCDs in turn (block b to XCD b mod 8), each XCD with
+    // its own L2.  Give XCD k the k-th contiguous eighth of the tiles (x fastest, then z, then
+    // the row chunk), so that the tiles whose halos overlap share one L2.
+    const int gx = (c.nx + BX - 1) / BX, gz = (c.nz + BZ - 1) / BZ;
+    const int ntiles = gridDim.x;
+    const int blk = blockIdx.x, xcd = blk & 7, per = ntiles >> 3, rem = ntiles & 7;
+    const int t = xcd * per + min(xcd, rem) + (blk >> 3);
+    const int xb = (t % gx) * BX, zb = ((t / gx) % gz) * BZ;
+    const int yb = (t / gx / gz) * cy, ye = min(yb + cy, c.ny);
     // Tile columns past the edge of the box hold the periodic images of nodes (as many times over
     // as needed when the box is narrower than the tile), so the LDS neighbours of every active
     // column are the true periodic neighbours; only active threads collide and store.
@@ -247,7 +255,7 @@ k3_fused(const Chan3* __restrict__ cp, float* __restrict__ ws, int src, int cy) 
     } else {
         hx = SX - 1; hz = 1 + tid - 2 * SX - BZ;
     }
-    const int gx = (xb - 1 + hx + c.nx) % c.nx, gz = (zb - 1 + hz + c.nz) % c.nz;
+    const int hxg = (xb - 1 + hx + c.nx) % c.nx, hzg = (zb - 1 + hz + c.nz) % c.nz;
     const bool halo = tid < NH;
     const int64_t comp_bytes = (int64_t)19 * c.plane * 4;
     const float* gsrc = ws + c.off + (int64_t)src * 38 * c.plane;
@@ -267,8 +275,8 @@ k3_fused(const Chan3* __restrict__ cp, float* __restrict__ ws, int src, int cy) 
         if (halo) {
             float h[38];
             float hA = 0.0f, hB = 0.0f;
-            if (!solid(c, gx, y, gz)) {
-                pull_any(rA, rB, Pb, c, gx, y, gz, h);
+            if (!solid(c, hxg, y, hzg)) {
+                pull_any(rA, rB, Pb, c, hxg, y, hzg, h);
                 hA = sum19(h);
                 hB = sum19(h + 19);
             }
@@ -497,8 +505,9 @@ hipError_t launch_step(const Chan3& h, const Chan3* c, float* ws, int src, hipSt
 hipError_t launch_step_fused(const Chan3& h, const Chan3* c, float* ws, int src, int cy, hipStream_t s) {
     constexpr int BX = 64, BZ = 4;
     cy = cy < 1 ? 1 : (cy > h.ny ? h.ny : cy);
-    const dim3 grid((h.nx + BX - 1) / BX, (h.nz + BZ - 1) / BZ, (h.ny + cy - 1) / cy);
-    hipLaunchKernelGGL((k3_fused<BX, BZ>), grid, dim3(BX * BZ), 0, s, c, ws, src, cy);
+    const int64_t ntiles = (int64_t)((h.nx + BX - 1) / BX) * ((h.nz + BZ - 1) / BZ) * ((h.ny + cy - 1) / cy);
+    if (ntiles > INT32_MAX) return hipErrorInvalidConfiguration;
+    hipLaunchKernelGGL((k3_fused<BX, BZ>), dim3((unsigned)ntiles), dim3(BX * BZ), 0, s, c, ws, src, cy);
     return hipGetLastError();
 }
 
