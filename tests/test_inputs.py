@@ -70,3 +70,15 @@ def test_rough_mask_geometry():
     a, b = case.fields()
     assert np.all(a[m] == 0) and np.all(b[m] == 0) and np.all(a[~m] > 0)
     assert g == inputs.Geometry(g.nx, g.ny, g.x0, g.x1)      # the mask is not part of equality
+
+
+def test_instability_golden_case_is_the_sweep_channel():
+    """The oracle-written golden file describes the channel the sweep recipe draws today."""
+    import json
+    import os
+    ref = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "sweep_instability_H20_L512_r2.json")))
+    c = inputs.sweep_draws(64, seed=0)[ref["case"]["index"]]
+    g = c.geom
+    assert (c.name, g.nx, g.ny, g.x0, g.x1, c.seed) == (ref["case"]["name"], ref["case"]["nx"], ref["case"]["ny"],
+                                                      ref["case"]["x0"], ref["case"]["x1"], ref["case"]["noise_seed"])
+    assert list(c.params.tau) == ref["case"]["tau"] and list(c.params.gw) == ref["case"]["gw"]
