@@ -431,6 +431,9 @@ k_step_fused2(const Chan* __restrict__ chans, const TileDesc* __restrict__ tiles
     __shared__ float r2[2][3][BX];       // n(t + 1)
     __shared__ float eR[NW][6];          // lane 63 of each wave: f*_1, f*_5, f*_8 (A, B)
     __shared__ float eL[NW][6];          // lane 0 of each wave:  f*_3, f*_6, f*_7 (A, B)
+    // rows awaiting collision, one slot per lane (each lane reads and writes only its own)
+    __shared__ float sq[18][BX];         // stage 1: pulled populations of the previous row
+    __shared__ float sq2[18][BX];        // stage 2: pulled populations of the previous row
     const int tid = threadIdx.x;
     const int lane = tid & 63, wv = tid >> 6;
     const int opp[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
@@ -448,17 +451,16 @@ k_step_fused2(const Chan* __restrict__ chans, const TileDesc* __restrict__ tiles
         const int Pb = (int)(c.plane * 4);
         const int hx = wrap_mod(tid == 0 ? td.xb - 3 : td.xb + w + 2, c.nx);
         const int hslot = tid == 0 ? 0 : w + 5;
-        // stage 1: pulled row awaiting collision
-        float q[18];
+        // stage 1: densities and code of the pulled row awaiting collision (its populations wait
+        // in sq)
         float qA = 0.0f, qB = 0.0f;
         uint32_t qcode = 0;
         // stage 2: shifted f*(t) of the last two stage-1 rows (dirs 0,1,3,2,5,6 and 2,5,6 per
-        // component), own unshifted f*(t) of the last row, pulled row awaiting collision
-        float gm1[12], gm2[6], uf[14], q2[18];   // uf: directions 1,3,4,5,6,7,8 per component
+        // component), own unshifted f*(t) of the last row; the pulled row awaiting collision
+        // waits in sq2
+        float gm1[12], gm2[6], uf[14];   // uf: directions 1,3,4,5,6,7,8 per component
         float q2A = 0.0f, q2B = 0.0f;
         uint32_t q2code = 0;
-#pragma unroll
-        for (int i = 0; i < 18; ++i) q[i] = q2[i] = 0.0f;
 #pragma unroll
         for (int i = 0; i < 14; ++i) uf[i] = 0.0f;
 #pragma unroll
@@ -468,35 +470,45 @@ k_step_fused2(const Chan* __restrict__ chans, const TileDesc* __restrict__ tiles
         const int niter = td.ye - td.yb + 6;
         // the stage-1 pull of row a + 1 is issued during iteration k (after the second barrier)
         // so that its latency overlaps the stage-2 work of the row
-        float pn[18];
+        float pn[18], hn[18];   // the row's pull and, on lanes 0 and 1, its halo column's
         uint32_t pcode = pull_node_buf<MASK>(rs, Pb, c, ws, x, wrap_mod(td.yb - 3, c.ny), pn);
+        uint32_t hcode = 0;
+        if (tid < 2) hcode = pull_node_buf<MASK>(rs, Pb, c, ws, hx, wrap_mod(td.yb - 3, c.ny), hn);
         for (int k = 0; k < niter; ++k) {
             const int s0 = k % 3, s1 = (k + 2) % 3, s2 = (k + 1) % 3;   // iterations k, k-1, k-2
             // A: stage-1 pull of row a (issued one iteration ago), densities n(t) into r1
             const int a = wrap_mod(td.yb - 3 + k, c.ny);
-            float p[18];
-#pragma unroll
-            for (int i = 0; i < 18; ++i) p[i] = pn[i];
             const uint32_t code = pcode;
             float nA = 0.0f, nB = 0.0f;
             if (!(code & 1u)) {
-                nA = sum9(p);
-                nB = sum9(p + 9);
+                nA = sum9(pn);
+                nB = sum9(pn + 9);
+            }
+            // the previous row's populations out of the lane's slot, this row's in
+            float q[18];
+#pragma unroll
+            for (int i = 0; i < 18; ++i) {
+                q[i] = sq[i][tid];
+                sq[i][tid] = pn[i];
             }
             if (in1) {
                 r1[0][s0][tid + 1] = nA;
                 r1[1][s0][tid + 1] = nB;
             }
             if (tid < 2) {
-                float h[18];
-                const uint32_t hcode = pull_node_buf<MASK>(rs, Pb, c, ws, hx, a, h);
                 float hA = 0.0f, hB = 0.0f;
                 if (!(hcode & 1u)) {
-                    hA = sum9(h);
-                    hB = sum9(h + 9);
+                    hA = sum9(hn);
+                    hB = sum9(hn + 9);
                 }
                 r1[0][s0][hslot] = hA;
                 r1[1][s0][hslot] = hB;
+            }
+            // the next row's stage-1 loads overlap the rest of the iteration
+            if (k + 1 < niter) {
+                const int an = a == c.ny - 1 ? 0 : a + 1;
+                pcode = pull_node_buf<MASK>(rs, Pb, c, ws, x, an, pn);
+                if (tid < 2) hcode = pull_node_buf<MASK>(rs, Pb, c, ws, hx, an, hn);
             }
             __syncthreads();
             // B: stage-1 collision of row a - 1 into registers, then the x part of streaming
@@ -541,7 +553,6 @@ k_step_fused2(const Chan* __restrict__ chans, const TileDesc* __restrict__ tiles
                 g[3] = eL[wv + 1][0]; g[6] = eL[wv + 1][1]; g[7] = eL[wv + 1][2];
                 g[12] = eL[wv + 1][3]; g[15] = eL[wv + 1][4]; g[16] = eL[wv + 1][5];
             }
-            if (k + 1 < niter) pcode = pull_node_buf<MASK>(rs, Pb, c, ws, x, a == c.ny - 1 ? 0 : a + 1, pn);
             // C: stage-2 pull of row b = a - 2: directions 0,1,3 from row b, 2,5,6 from row
             // b - 1, 4,7,8 from row b + 1 (this iteration's shifted values)
             float f2[18];
@@ -587,6 +598,12 @@ k_step_fused2(const Chan* __restrict__ chans, const TileDesc* __restrict__ tiles
             }
             r2[0][s0][tid] = n2A;
             r2[1][s0][tid] = n2B;
+            float q2[18];
+#pragma unroll
+            for (int i = 0; i < 18; ++i) {
+                q2[i] = sq2[i][tid];
+                sq2[i][tid] = f2[i];
+            }
             __syncthreads();
             // D: stage-2 collision of row b - 1 (pulled one iteration ago), store f*(t + 1)
             if (k >= 6 && in2 && !(q2code & 1u)) {
@@ -598,11 +615,6 @@ k_step_fused2(const Chan* __restrict__ chans, const TileDesc* __restrict__ tiles
                 if (q2code) wall_sum(q2code, swx, swy);
                 collide_store(c, q2, q2A, q2B, sAx, sAy, sBx, sBy, swx, swy,
                               BufferOutCached{rd, Pb, (yc * c.pitch + x) * 4});
-            }
-#pragma unroll
-            for (int i = 0; i < 18; ++i) {
-                q[i] = p[i];
-                q2[i] = f2[i];
             }
 #pragma unroll
             for (int m = 0; m < 2; ++m) {
