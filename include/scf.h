@@ -96,7 +96,7 @@ typedef struct {
                              contiguous eighth of that order instead of every 8th tile) */
     int32_t graph_steps;  /* steps per captured HIP graph, 0 = launch every step directly */
     int32_t fuse;         /* time steps per pass of the fused step: 1, or 2 (temporal blocking:
-                             each launch advances two steps, its tiles are bx - 4 columns wide,
+                             each launch advances two steps, its tiles are bx - 6 columns wide,
                              480 for bx = 512, and the intermediate populations stay on chip; an
                              odd remainder of a step count is done by one single step).  Same
                              results bit for bit. */

@@ -375,20 +375,21 @@ k_step_fused(const Chan* __restrict__ chans, const TileDesc* __restrict__ tiles,
 
 // ---------------------------------------------------------------------------------------------
 // Two time steps per pass (temporal blocking).  A block of BX lanes owns the output columns
-// [xb, xb + w), w = the tile's width <= BX - 4, and rows [yb, ye).  Stage 1 is the single step above on the wider
-// window [xb - 2, xb + w + 2) (lane = column + 2 - xb), with the two density-halo columns
-// xb - 3 and xb + w + 2 pulled by lanes 0 and 1; its post-collision values f*(t) never leave
-// the chip.  Stage 2 streams them: the x part by whole-wave lane shifts (DPP; the lanes at a
-// wave's edge take their neighbour's values through LDS), the y part by keeping the shifted
-// rows in registers; bounce-back uses the node's own unshifted f*(t).  Stage 2 then forms
-// n(t+1) into a second density ring and collides, storing f*(t+1).  Rows lag: iteration k
-// pulls row yb-3+k, stage 1 collides row yb-4+k, stage 2 pulls row yb-5+k and collides and
-// stores row yb-6+k.  Three barriers per row: after the stage-1 densities, after the edge
-// values, after the stage-2 densities.  Each node is computed with exactly the arithmetic of
-// the single step, so two stages equal two single steps bit for bit.  The stage-1 loads of the
-// next row are issued after the second barrier, so their latency overlaps stage 2.  The
-// kernel is held to three waves per SIMD (at most 168 VGPRs, a few spilled): faster than two
-// waves with the registers it would otherwise take, and than four with more spills.
+// [xb, xb + w), w = the tile's width <= BX - 6, and rows [yb, ye); lane l holds column
+// xb - 3 + l.  Stage 1 is the single step above, pulled on all w + 6 columns and collided on the
+// w + 4 inner ones; its post-collision values f*(t) never leave the chip.  Stage 2 streams them:
+// the x part by whole-wave lane shifts (DPP; the lanes at a wave's edge take their neighbour's
+// values through LDS), the y part by keeping the shifted rows in registers; bounce-back uses the
+// node's own unshifted f*(t).  Stage 2 then forms n(t+1) on the w + 2 columns around the output
+// into a second density ring and collides the w output columns, storing f*(t+1).  Rows lag:
+// iteration k pulls row yb-3+k, stage 1 collides row yb-4+k, stage 2 pulls row yb-5+k and
+// collides and stores row yb-6+k.  Three barriers per row: after the stage-1 densities, after
+// the edge values, after the stage-2 densities.  The pulled rows that wait one iteration for
+// their collision (one per stage) wait in per-lane LDS slots rather than in registers (copying
+// them between registers cost about a sixth of the loop's vector instructions), and the next
+// row's loads are issued as soon as the current row is in its slot, a whole iteration ahead.
+// Each node is computed with exactly the arithmetic of the single step, so two stages equal two
+// single steps bit for bit.  LDS (12 KB per wave) holds the kernel to three waves per SIMD.
 // ---------------------------------------------------------------------------------------------
 struct RegOut {
     float* r;
@@ -427,7 +428,7 @@ __global__ void __launch_bounds__(BX) __attribute__((amdgpu_waves_per_eu(3, 3)))
 k_step_fused2(const Chan* __restrict__ chans, const TileDesc* __restrict__ tiles, int ntiles,
               float* __restrict__ ws, int src) {
     constexpr int NW = BX / 64;
-    __shared__ float r1[2][3][BX + 2];   // n(t): slot 0 and w + 5 are the halo columns
+    __shared__ float r1[2][3][BX];       // n(t)
     __shared__ float r2[2][3][BX];       // n(t + 1)
     __shared__ float eR[NW][6];          // lane 63 of each wave: f*_1, f*_5, f*_8 (A, B)
     __shared__ float eL[NW][6];          // lane 0 of each wave:  f*_3, f*_6, f*_7 (A, B)
@@ -442,15 +443,14 @@ k_step_fused2(const Chan* __restrict__ chans, const TileDesc* __restrict__ tiles
         if (td.ye <= td.yb) continue;
         const Chan c = chans[td.chan];
         const int w = min(td.w, c.nx - td.xb);
-        const bool in1 = tid < w + 4;
-        const bool in2 = tid >= 2 && tid < w + 2;
-        const int x = wrap_mod(td.xb - 2 + min(tid, w + 3), c.nx);
+        const bool in1 = tid < w + 6;                  // pulled columns xb - 3 .. xb + w + 2
+        const bool c1 = tid >= 1 && tid < w + 5;       // stage-1 collisions
+        const bool in2 = tid >= 3 && tid < w + 3;      // stage-2 collisions: the output columns
+        const int x = wrap_mod(td.xb - 3 + min(tid, w + 5), c.nx);
         const int64_t buf_bytes = (int64_t)18 * c.plane * 4;
         const __amdgpu_buffer_rsrc_t rs = make_rsrc(ws + c.off + (int64_t)src * 18 * c.plane, buf_bytes);
         const __amdgpu_buffer_rsrc_t rd = make_rsrc(ws + c.off + (int64_t)(src ^ 1) * 18 * c.plane, buf_bytes);
         const int Pb = (int)(c.plane * 4);
-        const int hx = wrap_mod(tid == 0 ? td.xb - 3 : td.xb + w + 2, c.nx);
-        const int hslot = tid == 0 ? 0 : w + 5;
         // stage 1: densities and code of the pulled row awaiting collision (its populations wait
         // in sq)
         float qA = 0.0f, qB = 0.0f;
@@ -470,10 +470,8 @@ k_step_fused2(const Chan* __restrict__ chans, const TileDesc* __restrict__ tiles
         const int niter = td.ye - td.yb + 6;
         // the stage-1 pull of row a + 1 is issued during iteration k (after the second barrier)
         // so that its latency overlaps the stage-2 work of the row
-        float pn[18], hn[18];   // the row's pull and, on lanes 0 and 1, its halo column's
+        float pn[18];
         uint32_t pcode = pull_node_buf<MASK>(rs, Pb, c, ws, x, wrap_mod(td.yb - 3, c.ny), pn);
-        uint32_t hcode = 0;
-        if (tid < 2) hcode = pull_node_buf<MASK>(rs, Pb, c, ws, hx, wrap_mod(td.yb - 3, c.ny), hn);
         for (int k = 0; k < niter; ++k) {
             const int s0 = k % 3, s1 = (k + 2) % 3, s2 = (k + 1) % 3;   // iterations k, k-1, k-2
             // A: stage-1 pull of row a (issued one iteration ago), densities n(t) into r1
@@ -492,32 +490,22 @@ k_step_fused2(const Chan* __restrict__ chans, const TileDesc* __restrict__ tiles
                 sq[i][tid] = pn[i];
             }
             if (in1) {
-                r1[0][s0][tid + 1] = nA;
-                r1[1][s0][tid + 1] = nB;
-            }
-            if (tid < 2) {
-                float hA = 0.0f, hB = 0.0f;
-                if (!(hcode & 1u)) {
-                    hA = sum9(hn);
-                    hB = sum9(hn + 9);
-                }
-                r1[0][s0][hslot] = hA;
-                r1[1][s0][hslot] = hB;
+                r1[0][s0][tid] = nA;
+                r1[1][s0][tid] = nB;
             }
             // the next row's stage-1 loads overlap the rest of the iteration
             if (k + 1 < niter) {
                 const int an = a == c.ny - 1 ? 0 : a + 1;
                 pcode = pull_node_buf<MASK>(rs, Pb, c, ws, x, an, pn);
-                if (tid < 2) hcode = pull_node_buf<MASK>(rs, Pb, c, ws, hx, an, hn);
             }
             __syncthreads();
             // B: stage-1 collision of row a - 1 into registers, then the x part of streaming
             float fs[18];
 #pragma unroll
             for (int i = 0; i < 18; ++i) fs[i] = 0.0f;
-            if (k >= 2 && in1 && !(qcode & 1u)) {
+            if (k >= 2 && c1 && !(qcode & 1u)) {
                 float sAx, sAy, sBx, sBy;
-                ring_sums(r1[0][s2], r1[0][s1], r1[0][s0], r1[1][s2], r1[1][s1], r1[1][s0], tid + 1,
+                ring_sums(r1[0][s2], r1[0][s1], r1[0][s0], r1[1][s2], r1[1][s1], r1[1][s0], tid,
                           sAx, sAy, sBx, sBy);
                 float swx = 0.0f, swy = 0.0f;
                 if (qcode) wall_sum(qcode, swx, swy);

@@ -94,8 +94,8 @@ struct Layout {
     int nrows = 0, max_tiles = 0;
 };
 
-// Most tiles one list can hold: 60-column strips (bx = 64 with two steps per pass), cy = 1.
-int max_tiles_of(const scf_geometry& g) { return ((g.nx + 59) / 60) * g.ny; }
+// Most tiles one list can hold: 58-column strips (bx = 64 with two steps per pass), cy = 1.
+int max_tiles_of(const scf_geometry& g) { return ((g.nx + 57) / 58) * g.ny; }
 
 Layout plan(int nchan, const scf_geometry* g, int max_samples) {
     Layout L;
@@ -240,7 +240,7 @@ struct Engine {
     // Output columns per block of the two-step kernel: bx - 4 (it computes stage 1 on two
     // extra columns each side), rounded down to 32 columns for 512-wide blocks so that strip
     // edges fall on 128-byte lines (measured faster there; narrower blocks lose too much).
-    static int strip2(int bxv) { return bxv == 512 ? 480 : bxv - 4; }
+    static int strip2(int bxv) { return bxv == 512 ? 480 : bxv - 6; }
 
     int upload_tiles(int bxv, int cyv, int ord) {
         std::vector<scf::TileDesc> tl = make_tiles(bxv, cyv, ord);
