@@ -63,7 +63,7 @@ struct TileDesc {
 hipError_t launch_init(const Chan* chans, const RowRef* rows, int nrows, float* ws, hipStream_t s);
 hipError_t launch_step_fused(int bx, bool masked, const Chan* chans, const TileDesc* tiles,
                              int ntiles, int grid, float* ws, int src, hipStream_t s);
-// Two time steps in one pass; each tile carries its output width w <= bx - 4 (see k_step_fused2).
+// Two time steps in one pass; each tile carries its output width w <= bx - 6 (see k_step_fused2).
 hipError_t launch_step_fused2(int bx, bool masked, const Chan* chans, const TileDesc* tiles,
                               int ntiles, int grid, float* ws, int src, hipStream_t s);
 hipError_t launch_step_two_kernel(const Chan* chans, const RowRef* rows, int nrows, float* ws,

@@ -199,7 +199,7 @@ struct Engine {
     // round-robin to the 8 XCDs; with SCF_ORDER_XCD the list is permuted so that each XCD gets
     // a contiguous eighth of the base order (empty tiles pad the last round).
     std::vector<scf::TileDesc> make_tiles(int bxv, int cyv, int ord) const {
-        // bxv is the strip width: bx for single steps, bx - 4 for two steps per pass
+        // bxv is the strip width: bx for single steps, strip2(bx) for two steps per pass
         const bool bands = (ord & SCF_ORDER_BANDS) != 0;
         std::vector<scf::TileDesc> tl;
         for (int c = 0; c < nchan; ++c) {
@@ -237,9 +237,9 @@ struct Engine {
         return out;
     }
 
-    // Output columns per block of the two-step kernel: bx - 4 (it computes stage 1 on two
-    // extra columns each side), rounded down to 32 columns for 512-wide blocks so that strip
-    // edges fall on 128-byte lines (measured faster there; narrower blocks lose too much).
+    // Output columns per block of the two-step kernel: bx - 6 (its lanes pull three extra
+    // columns each side), 480 for 512-wide blocks so that strip edges fall on 128-byte lines
+    // (measured faster there; narrower blocks lose too much).
     static int strip2(int bxv) { return bxv == 512 ? 480 : bxv - 6; }
 
     int upload_tiles(int bxv, int cyv, int ord) {
