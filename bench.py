@@ -40,6 +40,7 @@ import json
 import os
 import sys
 import time
+from typing import Optional
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
@@ -49,26 +50,33 @@ HBM_PEAK_GBS = 8000.0
 BYTES_PER_LUP = {"fused": 144, "two_kernel": 232}
 KERNEL_SRC = os.path.join(ROOT, "paper_0807_0602_amd", "csrc", "scf_kernels.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_step_fused_capillary_16384x1024_traffic.json")
+KERNEL3_SRC = os.path.join(ROOT, "paper_0807_0602_amd", "csrc", "scf3d_kernels.hip")
+TRAFFIC3_FILE = os.path.join(ROOT, "profiles", "k3_fused_duct3d_512x182x182_traffic.json")
+DUCT3D = (512, 182, 182, 128, 384)   # nx, ny, nz, x0, x1 of the 3-D duct workload
 
 
-def kernel_hash() -> str:
-    with open(KERNEL_SRC, "rb") as f:
+def kernel_hash(src: Optional[str] = None) -> str:
+    with open(src or KERNEL_SRC, "rb") as f:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def measured_traffic(cells: int, schedule: dict):
-    """HBM bytes per launch of the fused step from the committed counter summary for this
-    schedule, or None if the kernel source changed since the counters were taken."""
+def measured_traffic(cells: int, schedule: dict, path: Optional[str] = None, src: Optional[str] = None,
+                     keys=("bx", "cy", "order", "fuse")):
+    """HBM bytes per launch of a fused step from the committed counter summary for this
+    schedule (the 2-D capillary's file by default), or None if the kernel source changed since
+    the counters were taken."""
+    path = path or TRAFFIC_FILE
+    src = src or KERNEL_SRC
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(path) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
-    if t.get("kernel_sha256_16") != kernel_hash() or t.get("cells") != cells:
+    if t.get("kernel_sha256_16") != kernel_hash(src) or t.get("cells") != cells:
         return None
     for e in t.get("schedules", []):
         if all(e["schedule"].get(k, 1 if k == "fuse" else None) == schedule.get(k, 1 if k == "fuse" else None)
-               for k in ("bx", "cy", "order", "fuse")):
+               for k in keys):
             return e["bytes_per_launch"]
     return None
 
@@ -100,31 +108,42 @@ def summarize_counters(args) -> int:
     calibration copy into TRAFFIC_FILE (one entry per schedule).  Each counter is scaled by
     (bytes the copy kernel moves) / (what the counter reads for it)."""
     fetch, write, fetch_copy, write_copy = args.summarize_counters
-    bx, cy, order, fuse = args.tile
-    kname = kernel_name(fuse) + "<"    # template instantiations only (not the other kernel)
+    if args.workload == "duct3d":
+        if args.cy3 < 1:
+            raise SystemExit("counter summaries of the 3-D duct cover the fused step (--cy3 >= 1)")
+        kname, path, src, label = "k3_fused<", TRAFFIC3_FILE, KERNEL3_SRC, "k3_fused"
+        nx, ny, nz = DUCT3D[:3]
+        cells, workload = nx * ny * nz, "duct3d_%dx%dx%d" % (nx, ny, nz)
+        sched = {"cy": min(args.cy3, ny)}
+    else:
+        if not args.tile:
+            raise SystemExit("--summarize-counters needs --tile BX CY ORDER")
+        bx, cy, order, fuse = args.tile
+        kname = kernel_name(fuse) + "<"    # template instantiations only (not the other kernel)
+        path, src, label = TRAFFIC_FILE, KERNEL_SRC, "k_step_fused / k_step_fused2"
+        from paper_0807_0602_amd import inputs
+        case = inputs.capillary_roofline(seed=1)
+        cells, workload = case.geom.nx * case.geom.ny, case.name
+        sched = {"bx": bx, "cy": cy, "order": order, "fuse": fuse}
     copy_kib = (1 << 30) / 1024.0
     f_scale = copy_kib / _counter_mean(fetch_copy, "copyBuffer", "FETCH_SIZE")
     w_scale = copy_kib / _counter_mean(write_copy, "copyBuffer", "WRITE_SIZE")
     rd = _counter_mean(fetch, kname, "FETCH_SIZE") * f_scale * 1024.0
     wr = _counter_mean(write, kname, "WRITE_SIZE") * w_scale * 1024.0
-    from paper_0807_0602_amd import inputs
-    case = inputs.capillary_roofline(seed=1)
-    cells = case.geom.nx * case.geom.ny
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(path) as f:
             t = json.load(f)
     except (OSError, ValueError):
         t = {}
-    if t.get("kernel_sha256_16") != kernel_hash() or t.get("cells") != cells:
-        t = {"kernel": "k_step_fused / k_step_fused2", "workload": case.name, "cells": cells,
-             "kernel_sha256_16": kernel_hash(), "schedules": []}
-    sched = {"bx": bx, "cy": cy, "order": order, "fuse": fuse}
+    if t.get("kernel_sha256_16") != kernel_hash(src) or t.get("cells") != cells:
+        t = {"kernel": label, "workload": workload, "cells": cells,
+             "kernel_sha256_16": kernel_hash(src), "schedules": []}
     t["schedules"] = [e for e in t["schedules"] if e["schedule"] != sched]
     t["schedules"].append({"schedule": sched, "read_bytes_per_launch": round(rd),
                            "write_bytes_per_launch": round(wr), "bytes_per_launch": round(rd + wr),
                            "read_bytes_per_node": round(rd / cells, 2), "write_bytes_per_node": round(wr / cells, 2),
                            "fetch_scale": round(f_scale, 4), "write_scale": round(w_scale, 4)})
-    with open(TRAFFIC_FILE, "w") as f:
+    with open(path, "w") as f:
         json.dump(t, f, indent=1)
     print(json.dumps(t["schedules"][-1]))
     return 0
@@ -289,7 +308,7 @@ def duct3d(args) -> int:
     from paper_0807_0602_amd import inputs
     from paper_0807_0602_amd.scf import Channel3
 
-    nx, ny, nz, x0, x1 = 512, 182, 182, 128, 384
+    nx, ny, nz, x0, x1 = DUCT3D
     steps = args.steps if args.steps != 10000 else 1000
     Z, Y, X = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
     liq = X < x0
@@ -320,6 +339,8 @@ def duct3d(args) -> int:
     # reads the density field once (16 B) and stores 152 B
     bpl = 304 if fused else 472
     achieved = bpl * cells / step_s / 1e9
+    sched = ch.schedule()
+    traffic = measured_traffic(cells, {"cy": sched["cy"]}, TRAFFIC3_FILE, KERNEL3_SRC, ("cy",)) if fused else None
     line = {
         "metric": "D3Q19 binary-SC MLUPS (3-D duct capillary)", "value": round(cells * steps / wall / 1e6, 1),
         "unit": "MLUPS", "n_gpus": 1, "steps": steps, "warmup": min(args.warmup, 50),
@@ -328,8 +349,9 @@ def duct3d(args) -> int:
         "config": {"workload": "duct3d_512x182x182", "nx": nx, "ny": ny, "nz": nz, "channel_x": [x0, x1],
                    "G": 0.9, "gw": [-0.2, 0.2], "tau": [1.0, 1.0], "nodes": cells},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": ("k3_fused, %d rows of y per 64 x 4 tile" % ch.schedule()["cy"]) if fused
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "traffic_gbs": round(traffic / step_s / 1e9, 1) if traffic else None,
+                     "kernel": ("k3_fused, %d rows of y per 64 x 4 tile" % sched["cy"]) if fused
                      else "k3_density + k3_collide", "bytes_per_node_update": bpl,
                      "event_ms_per_step": round(step_s * 1e3, 5)},
         "health": {"flags": obs["flags"], "z": obs["z"], "mass": list(obs["mass"])},
@@ -435,8 +457,6 @@ def main() -> int:
     args = ap.parse_args()
     args.tile = parse_tile(args.tile)
     if args.summarize_counters:
-        if not args.tile:
-            raise SystemExit("--summarize-counters needs --tile BX CY ORDER")
         return summarize_counters(args)
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: the library has no multi-GPU path (a channel "

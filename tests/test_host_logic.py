@@ -78,6 +78,7 @@ def test_bench_counter_summary(tmp_path, monkeypatch):
 
     class A:
         summarize_counters = files
+        workload = "roofline"
         tile = bench.parse_tile([256, 16, 1])
     assert A.tile == (256, 16, 1, 1)
     assert bench.summarize_counters(A) == 0
@@ -100,11 +101,34 @@ def test_bench_counter_summary(tmp_path, monkeypatch):
 
     class B:
         summarize_counters = files2 + files[2:]
+        workload = "roofline"
         tile = bench.parse_tile([256, 16, 1, 2])
     assert bench.summarize_counters(B) == 0
     t = json.load(open(tmp_path / "traffic.json"))
     assert len(t["schedules"]) == 2
     assert bench.measured_traffic(cells, {"bx": 256, "cy": 16, "order": 1, "fuse": 2}) == (900000 * 2 + 1179000) * 1024
+    # the 3-D duct: k3_fused counters into their own file, keyed by the rows per tile
+    monkeypatch.setattr(bench, "TRAFFIC3_FILE", str(tmp_path / "traffic3.json"))
+    files3 = []
+    for name, kern, ctr, vals in [("f3", "k3_fused<4>", "FETCH_SIZE", [2900000]),
+                                  ("w3", "k3_fused<4>", "WRITE_SIZE", [2490000]),
+                                  ("fo", "k3_density", "FETCH_SIZE", [1])]:
+        p = str(tmp_path / f"{name}.csv")
+        _counter_csv(p, kern, ctr, vals)
+        files3.append(p)
+
+    class D:
+        summarize_counters = files3[:2] + files[2:]
+        workload = "duct3d"
+        cy3 = 16
+        tile = None
+    assert bench.summarize_counters(D) == 0
+    t3 = json.load(open(tmp_path / "traffic3.json"))
+    assert t3["cells"] == 512 * 182 * 182 and t3["schedules"][0]["schedule"] == {"cy": 16}
+    assert bench.measured_traffic(512 * 182 * 182, {"cy": 16}, bench.TRAFFIC3_FILE, bench.KERNEL3_SRC,
+                                  ("cy",)) == (2900000 * 2 + 2490000) * 1024
+    assert bench.measured_traffic(512 * 182 * 182, {"cy": 8}, bench.TRAFFIC3_FILE, bench.KERNEL3_SRC,
+                                  ("cy",)) is None
 
 
 def test_wetting_circle_fit_and_contour():
