@@ -468,8 +468,8 @@ k_step_fused2(const Chan* __restrict__ chans, const TileDesc* __restrict__ tiles
 #pragma unroll
         for (int i = 0; i < 6; ++i) gm2[i] = 0.0f;
         const int niter = td.ye - td.yb + 6;
-        // the stage-1 pull of row a + 1 is issued during iteration k (after the second barrier)
-        // so that its latency overlaps the stage-2 work of the row
+        // the stage-1 pull of row a + 1 is issued during iteration k as soon as row a is in its
+        // slot, so that its latency overlaps the rest of the iteration
         float pn[18];
         uint32_t pcode = pull_node_buf<MASK>(rs, Pb, c, ws, x, wrap_mod(td.yb - 3, c.ny), pn);
         for (int k = 0; k < niter; ++k) {
