@@ -116,20 +116,25 @@ def summarize_counters(args) -> int:
         cells, workload = nx * ny * nz, "duct3d_%dx%dx%d" % (nx, ny, nz)
         sched = {"cy": min(args.cy3, ny)}
     else:
-        if not args.tile:
-            raise SystemExit("--summarize-counters needs --tile BX CY ORDER")
-        bx, cy, order, fuse = args.tile
-        kname = kernel_name(fuse) + "<"    # template instantiations only (not the other kernel)
         path, src, label = TRAFFIC_FILE, KERNEL_SRC, "k_step_fused / k_step_fused2"
         from paper_0807_0602_amd import inputs
         case = inputs.capillary_roofline(seed=1)
         cells, workload = case.geom.nx * case.geom.ny, case.name
-        sched = {"bx": bx, "cy": cy, "order": order, "fuse": fuse}
+        if getattr(args, "variant", "fused") == "two_kernel":
+            # one step = one k_density and one k_collide launch
+            kname, sched = ("k_density(", "k_collide("), {"variant": "two_kernel"}
+        else:
+            if not args.tile:
+                raise SystemExit("--summarize-counters needs --tile BX CY ORDER")
+            bx, cy, order, fuse = args.tile
+            kname = kernel_name(fuse) + "<"    # template instantiations only (not the other kernel)
+            sched = {"bx": bx, "cy": cy, "order": order, "fuse": fuse}
     copy_kib = (1 << 30) / 1024.0
     f_scale = copy_kib / _counter_mean(fetch_copy, "copyBuffer", "FETCH_SIZE")
     w_scale = copy_kib / _counter_mean(write_copy, "copyBuffer", "WRITE_SIZE")
-    rd = _counter_mean(fetch, kname, "FETCH_SIZE") * f_scale * 1024.0
-    wr = _counter_mean(write, kname, "WRITE_SIZE") * w_scale * 1024.0
+    knames = kname if isinstance(kname, tuple) else (kname,)
+    rd = sum(_counter_mean(fetch, k, "FETCH_SIZE") for k in knames) * f_scale * 1024.0
+    wr = sum(_counter_mean(write, k, "WRITE_SIZE") for k in knames) * w_scale * 1024.0
     try:
         with open(path) as f:
             t = json.load(f)
@@ -518,7 +523,10 @@ def main() -> int:
     bpl = BYTES_PER_LUP[args.variant]
     # algorithmic bytes per launch: bpl per node update x the node updates of one launch
     achieved = bpl * cells * fuse / launch_s / 1e9
-    traffic = measured_traffic(cells, tile) if args.variant == "fused" else None
+    if args.variant == "fused":
+        traffic = measured_traffic(cells, tile)
+    else:
+        traffic = measured_traffic(cells, {"variant": "two_kernel"}, keys=("variant",))
     line = {
         "metric": METRIC, "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(wall * 1e3 / args.steps, 5),

@@ -107,6 +107,30 @@ def test_bench_counter_summary(tmp_path, monkeypatch):
     t = json.load(open(tmp_path / "traffic.json"))
     assert len(t["schedules"]) == 2
     assert bench.measured_traffic(cells, {"bx": 256, "cy": 16, "order": 1, "fuse": 2}) == (900000 * 2 + 1179000) * 1024
+    # the two-kernel variant: one k_density and one k_collide launch per step, summed
+    files4 = []
+    for name, kern, ctr, vals in [("f4", "k_density(scf::Chan const*)", "FETCH_SIZE", [700000]),
+                                  ("f4", None, None, None),
+                                  ("w4", "k_collide(scf::Chan const*)", "WRITE_SIZE", [1179000])]:
+        if kern is None:
+            continue
+        p = str(tmp_path / f"{name}.csv")
+        _counter_csv(p, kern, ctr, vals)
+        files4.append(p)
+    with open(files4[0], "a", newline="") as f:
+        csv.writer(f).writerow(["k_collide(scf::Chan const*)", "FETCH_SIZE", 900000])
+    with open(files4[1], "a", newline="") as f:
+        csv.writer(f).writerow(["k_density(scf::Chan const*)", "WRITE_SIZE", 131000])
+
+    class T:
+        summarize_counters = files4 + files[2:]
+        workload = "roofline"
+        variant = "two_kernel"
+        tile = None
+    assert bench.summarize_counters(T) == 0
+    assert bench.measured_traffic(cells, {"variant": "two_kernel"}, keys=("variant",)) == \
+        ((700000 + 900000) * 2 + 1179000 + 131000) * 1024
+    assert bench.measured_traffic(cells, {"bx": 256, "cy": 16, "order": 1, "fuse": 2}) == (900000 * 2 + 1179000) * 1024
     # the 3-D duct: k3_fused counters into their own file, keyed by the rows per tile
     monkeypatch.setattr(bench, "TRAFFIC3_FILE", str(tmp_path / "traffic3.json"))
     files3 = []
