@@ -149,7 +149,7 @@ int scf_set_variant(scf_ctx* ctx, int32_t variant);
 
 /* Set the launch schedule of the fused step: tiles of bx columns by cy rows (every other tile
  * of a strip walks its rows downward), taken by the blocks of one launch in the given order,
- * and one or two time steps per launch (fuse).  A new context starts with bx = 256, cy = 48,
+ * and one or two time steps per launch (fuse).  A new context starts with bx = 256, cy = 16,
  * order = SCF_ORDER_BANDS | SCF_ORDER_XCD, graph_steps = 64, fuse = 2.  Schedules change only the order of work, never
  * the result.  Invalidates captured graphs.  Errors: SCF_EINVAL (bx not 64/128/256/512,
  * cy < 1, unknown order, graph_steps < 0, fuse not 1 or 2). */

@@ -163,7 +163,7 @@ struct Engine {
     int64_t t = 0;
     int variant = SCF_VARIANT_FUSED;
     // default schedule: the one the autotuner picks for the 16384 x 1024 capillary
-    int bx = 256, cy = 48, order = SCF_ORDER_BANDS | SCF_ORDER_XCD, graph_steps = 64, grid = 0, fuse = 2;
+    int bx = 256, cy = 16, order = SCF_ORDER_BANDS | SCF_ORDER_XCD, graph_steps = 64, grid = 0, fuse = 2;
     int ntiles = 0, ntiles2 = 0;
     hipGraphExec_t g_steps[2] = {nullptr, nullptr};
     hipGraphExec_t g_sample[2] = {nullptr, nullptr};

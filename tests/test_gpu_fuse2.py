@@ -113,7 +113,7 @@ def test_fuse2_full_size_bitwise(scf):
     case = inputs.capillary_roofline(seed=1)
     _say("case: fuse2 full size 16384x1024, 4 steps")
     a = _run(scf, case, 4, bx=512, cy=8, graph_steps=0, order=1, fuse=1)
-    b = _run(scf, case, 4, bx=256, cy=48, graph_steps=0, order=3, fuse=2)
+    b = _run(scf, case, 4, bx=256, cy=16, graph_steps=0, order=3, fuse=2)
     na = a.density()
     nb = b.density()
     assert np.array_equal(na[0], nb[0]) and np.array_equal(na[1], nb[1])

@@ -279,7 +279,7 @@ def test_batch_against_oracle(scf):
 
 # ------------------------------------------------------------------------------ full sizes
 # the schedule bench.py's autotuner picks for the 16384 x 1024 capillary (two steps per launch)
-BENCH_TILE = dict(bx=256, cy=48, graph_steps=64, order=3, fuse=2)
+BENCH_TILE = dict(bx=256, cy=16, graph_steps=64, order=3, fuse=2)
 
 
 def _window_check(scf, case, T, centres, half, tile=BENCH_TILE):
