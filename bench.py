@@ -22,7 +22,7 @@ capillary), duct3d (MLUPS of the 3-D D3Q19 duct, 512 x 182 x 182).
 
 --workload surrogate measures the learned surrogate against the batched LBM on 64 fresh
 channels drawn like its training set (seed 3): the LBM simulates them (points/hour of the LBM)
-and judges the network's curves (max |z_surrogate - z_LBM| per channel, lattice units); the
+and scores the network's curves (max |z_surrogate - z_LBM| per channel, lattice units); the
 network's points/hour come from timed inference of the same curves.
 
 --workload sweep measures the batched calibration sweep instead: 64 channels with H in
@@ -294,7 +294,7 @@ def surrogate_gain(args) -> int:
         "dtype": "bf16 MFMA / f32 accumulate (network), f32 (LBM)", "data": "synthetic",
         "config": {"workload": "surrogate_vs_lbm_64_channels", "inputs": int(net.cfg.d_in),
                    "lbm_points_per_hour": round(lbm_pph, 1), "surrogate_points_per_hour": round(sur_pph, 1),
-                   "speedup": round(sur_pph / lbm_pph, 1), "judged_channels": int(ok.sum()),
+                   "speedup": round(sur_pph / lbm_pph, 1), "scored_channels": int(ok.sum()),
                    "max_dz_lu": float(np.nanmax(errs[:, 0])), "median_max_dz_lu": float(np.nanmedian(errs[:, 0])),
                    "fraction_within_1lu": round(within, 4),
                    "points_per_hour_within_1lu": round(sur_pph * within, 1),

@@ -1,6 +1,6 @@
 """Surrogate of the batched LBM: a network from sweep parameters and time to the front and
 precursor positions, trained on the GPU by the library's own MFMA kernels (scf_sur_* in
-include/scf.h), with the LBM as fallback outside the training range and as judge of its error.
+include/scf.h), with the LBM as fallback outside the training range and as the reference for its error.
 
 Features of one sample (A-S1 of the design notes: the 4-input set, optionally the channel
 length): (G_wA, log(tau_B / tau_A), H, log t[, log L]).  Targets: (z / H, p / H).  Sample

@@ -1,4 +1,4 @@
-"""What the trained surrogate gains over the LBM it replaces, judged by the LBM.
+"""What the trained surrogate gains over the LBM it replaces, scored against the LBM.
 
 Eight fresh channels are drawn like the training set (seed 5), simulated for 50 000 steps by the
 batched LBM and predicted by the committed 5-input network.  The network must answer the same
