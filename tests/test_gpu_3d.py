@@ -165,3 +165,30 @@ def test_schedule_rejects_bad_values(S):
         with pytest.raises(L.ScfError):
             ch.set_schedule(*bad)
     assert ch.schedule() == {"fused": True, "cy": 16}
+
+
+@pytest.mark.parametrize("tau", [(1.0, 0.55), (1.0, 0.6), (1.0, 1.0)])
+def test_health_flag_follows_the_oracle(S, tau):
+    """The literal viscosity-ratio pairs tau_B = 0.55, 0.6 lose positivity in 3-D as in 2-D: the
+    GPU's health flag (a non-finite density, or one below -1e-3 at a fluid node) is raised at the
+    same steps as the same test applied to the oracle's densities; tau = (1, 1) stays clean."""
+    nx, ny, nz, x0, x1 = 40, 10, 10, 10, 30
+    Z, Y, X = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    liq = X < 14
+    a = np.where(liq, 2.0, 0.06) + 1e-3 * inputs.uniform_pm1(9, 0, Y * nz + Z, X)
+    b = np.where(liq, 0.06, 2.0) + 1e-3 * inputs.uniform_pm1(9, 1, Y * nz + Z, X)
+    prm = inputs.Params(G=0.9, gw=(-0.2, 0.2), tau=tau)
+    ch = S.Channel3(nx, ny, nz, x0, x1, prm, a, b, walls_y=True, walls_z=True)
+    o = oracle.Oracle3(nx, ny, nz, x0, x1, walls_y=True, walls_z=True, G=0.9, gw=(-0.2, 0.2), tau=tau).init(a, b)
+    _say(f"case: 3-D health flag, tau={tau}")
+    flags = []
+    for t in range(1, 13):
+        ch.step(1)
+        o.step(1)
+        gpu_bad = bool(ch.observe(allow_unstable=True)["flags"] & 2)
+        nA, nB = o.density()
+        orc_bad = bool(not (np.isfinite(nA).all() and np.isfinite(nB).all()) or min(nA.min(), nB.min()) < -1e-3)
+        flags.append((t, gpu_bad, orc_bad))
+        assert gpu_bad == orc_bad, flags
+    _say(f"  flags (t, gpu, oracle): {flags}")
+    assert any(f[1] for f in flags) == (tau[1] < 1.0)
