@@ -291,6 +291,12 @@ def _window_check(scf, case, T, centres, half, tile=BENCH_TILE):
     ch.set_tile(**tile)
     ch.step(T)
     nA, nB = ch.density()
+    return _windows_of(case, nA, nB, T, centres, half)
+
+
+def _windows_of(case, nA, nB, T, centres, half):
+    """Largest density difference between the GPU fields (nA, nB after T steps) and the oracle
+    run on windows around the given columns (see _window_check)."""
     worst = 0.0
     nx = case.geom.nx
     for xc in centres:
@@ -326,6 +332,31 @@ def test_full_size_washburn_case_windows(scf):
                           tile=dict(bx=64, cy=8, graph_steps=64, order=3, fuse=2))
     _say(f"  max|drho| = {worst:.3e}")
     assert worst <= RHO_TOL
+
+
+def test_full_size_sweep_batch_windows(scf):
+    """The 64-channel calibration sweep at its full size (12.9 M nodes, one launch per two steps
+    for all channels) in the schedule the sweep bench's autotuner picks; oracle windows on the
+    longest and the shortest channel and on channel 27 (the one that loses stability late)."""
+    import torch
+    cases = inputs.sweep_draws(64, seed=0)
+    T = 50
+    _say(f"case: 64-channel sweep full size, {T} steps, oracle windows on three channels")
+    b = scf.Batch(cases, sample_every=100, max_samples=2)
+    b.set_tile(256, 8, graph_steps=100, order=1, fuse=2)
+    b.step(T)
+    nxs = [c.geom.nx for c in cases]
+    picks = sorted({int(np.argmax(nxs)), int(np.argmin(nxs)), 27})
+    worst = 0.0
+    for i in picks:
+        c = cases[i]
+        nA, nB = b.density(i)
+        g = c.geom
+        worst = max(worst, _windows_of(c, nA, nB, T, [g.x0, g.x1 - 1, 0], half=2 * T + 8))
+    _say(f"  channels {picks}: max|drho| = {worst:.3e}")
+    assert worst <= RHO_TOL
+    del b
+    torch.cuda.empty_cache()
 
 
 def test_full_size_roofline_case_mass_and_observables(scf):
