@@ -192,3 +192,32 @@ def test_health_flag_follows_the_oracle(S, tau):
         assert gpu_bad == orc_bad, flags
     _say(f"  flags (t, gpu, oracle): {flags}")
     assert any(f[1] for f in flags) == (tau[1] < 1.0)
+
+
+def test_full_size_duct_fused_equals_two_kernel(S):
+    """The 3-D bench duct at its full size (512 x 182 x 182, 17.0 M nodes) in the bench's launch
+    configuration (fused, 16 rows of y per tile): densities after 20 steps equal the two-kernel
+    step's bit for bit; mass is conserved to FP32 rounding and no flag is raised."""
+    import torch
+    nx, ny, nz, x0, x1 = 512, 182, 182, 128, 384
+    Z, Y, X = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    liq = X < x0
+    a = np.where(liq, 2.0, 0.06) + 1e-3 * inputs.uniform_pm1(1, 0, Y * nz + Z, X)
+    b = np.where(liq, 0.06, 2.0) + 1e-3 * inputs.uniform_pm1(1, 1, Y * nz + Z, X)
+    del Z, Y, X, liq
+    prm = inputs.Params(G=0.9, gw=(-0.2, 0.2))
+    _say("case: 3-D duct 512x182x182 full size, fused vs two-kernel, 20 steps")
+    out = []
+    for fused in (True, False):
+        ch = S.Channel3(nx, ny, nz, x0, x1, prm, a, b, walls_y=True, walls_z=True)
+        ch.set_schedule(fused=fused, cy=16)
+        m0 = ch.observe()["mass"]
+        ch.step(20)
+        o = ch.observe()
+        assert o["flags"] == 0
+        for k in range(2):
+            assert abs(o["mass"][k] - m0[k]) / m0[k] < 1e-5
+        out.append(ch.density())
+        del ch
+        torch.cuda.empty_cache()
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
