@@ -356,6 +356,7 @@ def duct3d(args) -> int:
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "traffic_gbs": round(traffic / step_s / 1e9, 1) if traffic else None,
+                     "traffic_frac": round(traffic / step_s / 1e9 / HBM_PEAK_GBS, 4) if traffic else None,
                      "kernel": ("k3_fused, %d rows of y per 64 x 4 tile" % sched["cy"]) if fused
                      else "k3_density + k3_collide", "bytes_per_node_update": bpl,
                      "event_ms_per_step": round(step_s * 1e3, 5)},
@@ -540,7 +541,10 @@ def main() -> int:
                      "kernel": kernel_name(fuse) if args.variant == "fused" else "k_density+k_collide",
                      "bytes_per_node_update": bpl, "steps_per_launch": fuse,
                      "event_ms_per_launch": round(launch_s * 1e3, 5),
-                     "traffic_gbs": round(traffic / launch_s / 1e9, 1) if traffic else None},
+                     "traffic_gbs": round(traffic / launch_s / 1e9, 1) if traffic else None,
+                     # measured HBM bytes per second over the peak (two steps per launch share
+                     # one read and one write, so `frac` can pass 1 while this cannot)
+                     "traffic_frac": round(traffic / launch_s / 1e9 / HBM_PEAK_GBS, 4) if traffic else None},
         "health": {"flags": obs["flags"], "z": obs["z"], "mass": list(obs["mass"])},
     }
     if not args.no_cpu_baseline:
