@@ -81,3 +81,43 @@ def test_3d_workspace_and_validation():
     rc = L.scf3_init(C.byref(h), C.byref(g), C.byref(p), None, None, None, 0, None)
     assert rc == L.SCF_EINVAL and b"alpha" in L.scf_last_error()
     assert L.scf3_set_schedule(None, 1, 16) == L.SCF_EINVAL
+
+
+def _prototypes():
+    """name -> (return type, [parameter types]) for every function prototype of include/scf.h."""
+    text = open(os.path.join(ROOT, "include", "scf.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    out = {}
+    for m in re.finditer(r"([A-Za-z_][A-Za-z0-9_ \*]*?)\b(scf3?_[a-z_0-9]+)\s*\(([^;{]*?)\)\s*;", text, flags=re.S):
+        ret, name, params = " ".join(m.group(1).split()), m.group(2), " ".join(m.group(3).split())
+        plist = [] if params in ("", "void") else [p.strip() for p in params.split(",")]
+        out[name] = (ret, plist)
+    return out
+
+
+def test_binding_signatures_match_the_header():
+    """Argument counts and scalar types of every binding entry agree with the prototypes."""
+    import ctypes as C
+    from paper_0807_0602_amd import _lib
+    protos = _prototypes()
+    assert set(protos) == set(_lib._sig), set(protos) ^ set(_lib._sig)
+    scalar = {"int": C.c_int, "int32_t": C.c_int32, "int64_t": C.c_int64, "size_t": C.c_size_t,
+              "float": C.c_float}
+    for name, (ret, params) in protos.items():
+        res, args = _lib._sig[name]
+        assert len(args) == len(params), (name, params, args)
+        # return type
+        r = ret.replace("const ", "").strip()
+        if r == "void":
+            assert res is None, name
+        elif r in scalar:
+            assert res is scalar[r], (name, r, res)
+        else:
+            assert r.endswith("*") and res is C.c_char_p, (name, r, res)
+        # scalar parameters map to their exact ctypes type, pointers to pointer-sized types
+        for p, a in zip(params, args):
+            words = p.replace("*", " * ").split()
+            if "*" in words:
+                assert a in (C.c_void_p, C.c_char_p) or issubclass(a, C._Pointer), (name, p, a)
+            else:
+                assert a is scalar[words[0]], (name, p, a)
