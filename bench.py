@@ -12,9 +12,12 @@ once and written once).
 Prints ONE JSON line.  Options: --steps K (timed), --warmup W, --gpus N (only 1 is supported),
 --variant fused|two_kernel, --no-cpu-baseline, --calibrate-copy (runs only a plain copy kernel,
 for counter calibration under rocprofv3), --tile BX CY ORDER [FUSE] (skip the autotuner; FUSE 2
-runs two time steps per launch).  With two steps per launch the roofline's `achieved` stays in
-the metric's unit, 144 bytes per node update (the bytes a single step moves), and `traffic`
-gives the measured bytes per launch.
+runs two time steps per launch), --cy3 N (duct3d: rows of y per tile, 0 = two kernels),
+--summarize-counters (fold rocprofv3 FETCH_SIZE / WRITE_SIZE CSVs into the committed traffic
+summaries).  With two steps per launch the roofline's `achieved` stays in the metric's unit, 144
+bytes per node update (the bytes a single step moves), `traffic` gives the measured HBM bytes
+per launch from the committed counter summary of the same kernel source, and `traffic_frac` the
+measured rate over the peak.
 
 Further workloads (--workload): small (the 200 x 24 parity capillary, microseconds per step for
 direct and graph launches and the oracle on the whole run), washburn (MLUPS on the 4096 x 202
@@ -27,8 +30,8 @@ network's points/hour come from timed inference of the same curves.
 
 --workload sweep measures the batched calibration sweep instead: 64 channels with H in
 {20, 40, 80, 160}, L in {512, ..., 4096}, G_wA uniform in [-0.3, 0.3] (G_wB = -G_wA) and a
-viscosity-ratio tau pair, advanced together (one launch per step over all their tiles, HIP
-graphs of 100 steps plus the recorded observation), 50 000 steps with z(t) and the precursor
+viscosity-ratio tau pair, advanced together (one launch per step or per two steps over all their
+tiles, HIP graphs of 100 steps plus the recorded observation), 50 000 steps with z(t) and the precursor
 recorded every 100 steps.  The value is sweep points per hour (one point = one channel's whole
 trajectory).
 """
