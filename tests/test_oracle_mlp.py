@@ -3,11 +3,13 @@
 * gradients against central finite differences (relative error <= 1e-6);
 * a one-unit network written out by hand (forward and gradient);
 * the first Adam step from zero moments equals lr * g / (|g| + eps) in closed form;
-* parameter counts of the 4- and 5-input networks (4 x 256 hidden, 2 outputs).
+* parameter counts of the 4- and 5-input networks (4 x 256 hidden, 2 outputs);
+* the committed trained weights are well formed (shapes, finite values, normalisation).
 """
 import math
 
 import numpy as np
+import pytest
 
 from oracle import mlp
 
@@ -59,3 +61,25 @@ def test_first_adam_step_closed_form():
     th, m, v = mlp.adam_update(np.zeros(4), g, np.zeros(4), np.zeros(4), step=1, lr=1e-3, eps=1e-8)
     np.testing.assert_allclose(th, -1e-3 * g / (np.abs(g) + 1e-8), rtol=1e-12, atol=1e-18)
     np.testing.assert_allclose(m, 0.1 * g); np.testing.assert_allclose(v, 0.001 * g * g)
+
+
+@pytest.mark.parametrize("d_in", [4, 5])
+def test_committed_weights_are_well_formed(d_in):
+    """The trained weights shipped with the package: the network of 4 hidden layers of 256 SiLU
+    units (199 170 or 199 426 parameters), finite values, a usable input normalisation, a finite
+    FP64 forward pass inside the training box, and the training record stored with them."""
+    import json
+    import os
+    path = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_0807_0602_amd",
+                        f"surrogate_weights_{d_in}in.npz")
+    z = np.load(path, allow_pickle=False)
+    assert int(z["d_in"]) == d_in and int(z["width"]) == 256 and int(z["depth"]) == 4
+    assert z["theta"].shape == (mlp.n_params(d_in),) == ({4: 199170, 5: 199426}[d_in],)
+    assert np.isfinite(z["theta"]).all()
+    assert (z["std"] > 0).all() and (z["lo"] < z["hi"]).all()
+    rng = np.random.default_rng(0)
+    X = z["lo"] + (z["hi"] - z["lo"]) * rng.random((64, d_in))
+    Y, _, _ = mlp.forward(z["theta"], (X - z["mean"]) / z["std"], d_in)
+    assert Y.shape == (64, 2) and np.isfinite(Y).all()
+    info = json.loads(str(z["info"]))
+    assert info["heldout_channels"] == 200 and 0.0 <= info["heldout_frac_le_1lu"] <= 1.0
