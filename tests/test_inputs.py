@@ -82,3 +82,22 @@ def test_instability_golden_case_is_the_sweep_channel():
     assert (c.name, g.nx, g.ny, g.x0, g.x1, c.seed) == (ref["case"]["name"], ref["case"]["nx"], ref["case"]["ny"],
                                                       ref["case"]["x0"], ref["case"]["x1"], ref["case"]["noise_seed"])
     assert list(c.params.tau) == ref["case"]["tau"] and list(c.params.gw) == ref["case"]["gw"]
+
+
+def test_instability_golden_regenerates_from_the_oracle(tmp_path, monkeypatch):
+    """The stored instability record is what the oracle-only script writes: rerunning it (to the
+    recorded step) reproduces the first unstable observation and every stored front exactly."""
+    import importlib.util
+    import json
+    import os
+    here = os.path.join(os.path.dirname(__file__), "golden")
+    ref = json.load(open(os.path.join(here, "sweep_instability_H20_L512_r2.json")))
+    spec = importlib.util.spec_from_file_location("make_sweep_instability",
+                                                  os.path.join(here, "make_sweep_instability.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    monkeypatch.setattr(mod, "HERE", str(tmp_path))
+    mod.main()
+    new = json.load(open(tmp_path / "sweep_instability_H20_L512_r2.json"))
+    assert new["first_unstable_t"] == ref["first_unstable_t"]
+    assert new["z_every_1000"] == ref["z_every_1000"]
