@@ -403,7 +403,12 @@ def small(args) -> int:
     o.step(steps)
     dto = time.perf_counter() - t0
     cells = case.geom.nx * case.geom.ny
-    best = min(v for k, v in out.items() if k.endswith("_us_per_step"))
+    timings = {k: v for k, v in out.items() if k.endswith("_us_per_step")}
+    best_key = min(timings, key=timings.get)
+    best = timings[best_key]
+    # the autotuned tile shape is shared by the four runs; `best` names the launch mode and the
+    # steps per launch of the reported value
+    out["best"] = best_key[: -len("_us_per_step")]
     line = {"metric": "microseconds per step, 200 x 24 capillary (launch-latency bound)", "value": best,
             "unit": "us/step", "n_gpus": 1, "steps": steps, "warmup": 200, "ms_per_step": best / 1e3,
             "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
