@@ -183,3 +183,12 @@ def test_wetting_match_and_pressure():
     rng = np.random.default_rng(3)
     a, b = rng.uniform(0, 2, 50), rng.uniform(0, 2, 50)
     assert np.allclose(W.eos_pressure(a, b, 0.9), physics.pressure(a, b, 0.9))
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py runs on exactly one GPU and says so when asked for more (before touching one)."""
+    import subprocess
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
