@@ -5,19 +5,27 @@ Workload: the roofline-scale capillary, a 16384 x 1024 box with walls over the c
 initial fields.  One step = one pass of the whole hot path (pull streaming with bounce-back,
 densities, bulk and wall forces, common velocity, shifted equilibrium, BGK collision, store)
 over every node.  The metric is MLUPS (million lattice-node updates per second, both
-components); the roofline object prices the fused step kernel against HBM bandwidth with the
-algorithmic traffic of 144 bytes per node update (2 components x 9 populations x 4 bytes, read
-once and written once).
+components); the roofline object prices the dominant kernel against HBM bandwidth with its
+algorithmic traffic per launch: 144 bytes per node (2 components x 9 populations x 4 bytes, read
+once and written once) whether the launch advances one time step or two (temporal blocking keeps
+the intermediate populations on chip).  `single_step_equiv_gbs` gives the same launch priced at
+144 bytes per node update, the bandwidth a one-step-per-launch kernel would need for the same
+MLUPS (it can pass the HBM peak).
+
+The default line also carries two sub-objects measured in the same run: `sweep`, the batched
+calibration sweep (64 channels of the sweep_64_channels draws, 50 000 steps each, samples every
+100 steps; points per hour, stable points per hour, aggregate MLUPS), and `surrogate`, the learned
+surrogate scored on the same 64 trajectories (points per hour of inference against the LBM's,
+the fraction of channels within 1 lattice unit of the LBM front and the largest error).
 
 Prints ONE JSON line.  Options: --steps K (timed), --warmup W, --gpus N (only 1 is supported),
 --variant fused|two_kernel, --no-cpu-baseline, --calibrate-copy (runs only a plain copy kernel,
 for counter calibration under rocprofv3), --tile BX CY ORDER [FUSE] (skip the autotuner; FUSE 2
 runs two time steps per launch), --cy3 N (duct3d: rows of y per tile, 0 = two kernels),
 --summarize-counters (fold rocprofv3 FETCH_SIZE / WRITE_SIZE CSVs into the committed traffic
-summaries).  With two steps per launch the roofline's `achieved` stays in the metric's unit, 144
-bytes per node update (the bytes a single step moves), `traffic` gives the measured HBM bytes
-per launch from the committed counter summary of the same kernel source, and `traffic_frac` the
-measured rate over the peak.
+summaries), --no-sweep (skip the sweep and surrogate sub-objects).  `traffic` gives the measured
+HBM bytes per launch from the committed counter summary of the same kernel source, and
+`traffic_frac` the measured rate over the peak.
 
 Further workloads (--workload): small (the 200 x 24 parity capillary, microseconds per step for
 direct and graph launches and the oracle on the whole run), washburn (MLUPS on the 4096 x 202
@@ -210,25 +218,28 @@ def calibrate_copy(nbytes: int = 1 << 30, reps: int = 5) -> None:
     print(json.dumps({"calibrate_copy_bytes": nbytes, "reps": reps}), flush=True)
 
 
-def sweep(args) -> int:
+def run_sweep(steps: int, tile=None, every: int = 100) -> dict:
+    """The batched calibration sweep (sweep_64_channels draws, seed 0) for `steps` steps with
+    z(t) and the precursor recorded every `every` steps; autotuned unless `tile` is given.
+    Returns the timing, the schedule, the cases and the trajectories [n, samples, 5] (t, z,
+    precursor, flags, unstable-so-far)."""
+    import numpy as np
     import torch
     from paper_0807_0602_amd import inputs
     from paper_0807_0602_amd.scf import Batch
 
-    steps = args.steps if args.steps != 10000 else 50_000
-    every = 100
     cases = inputs.sweep_draws(64, seed=0, steps=steps, sample_every=every)
     cells = sum(c.geom.nx * c.geom.ny for c in cases)
     stream = torch.cuda.current_stream()
     b = Batch(cases, sample_every=every, max_samples=steps // every + 1, stream=stream)
-    if args.tile:
-        bx, cy, order, fuse = args.tile
+    if tile:
+        bx, cy, order, fuse = tile
         b.set_tile(bx, cy, every, order, fuse)
     else:
         b.autotune(5)
         t = b.tile()
         b.set_tile(t["bx"], t["cy"], every, t["order"], t["fuse"])
-    tile = b.tile()
+    sched = b.tile()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
@@ -239,24 +250,87 @@ def sweep(args) -> int:
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     recs, ns = b.observe(allow_unstable=True)
-    unstable = sum(1 for r in recs if any(x["flags"] & 2 for x in r))
-    step_s = e0.elapsed_time(e1) / 1e3 / steps
-    achieved = 144 * cells / step_s / 1e9    # 144 B per node update (single-step equivalent)
+    b.close()
+    del b
+    torch.cuda.empty_cache()
+    traj = np.full((len(cases), ns, 5), np.nan)
+    for c, r in enumerate(recs):
+        bad = False
+        for k, x in enumerate(r):
+            bad = bad or bool(x["flags"] & 2)
+            traj[c, k] = (x["t"], x["z"], x["precursor"], x["flags"], float(bad))
+    unstable = int(sum(1 for r in recs if any(x["flags"] & 2 for x in r)))
+    return {"cases": cases, "traj": traj, "cells": cells, "wall": wall, "samples": ns,
+            "event_step_s": e0.elapsed_time(e1) / 1e3 / steps, "schedule": sched, "unstable": unstable}
+
+
+def score_surrogate(weights: str, cases, traj, lbm_wall: float, reps: int = 20) -> dict:
+    """The learned surrogate on the sweep's own channels: per-channel max |z_surrogate - z_LBM| in
+    lattice units over the LBM's samples (up to a channel's instability flag), and the network's
+    points per hour from timed inference of the same curves."""
+    import numpy as np
+    import torch
+    from paper_0807_0602_amd import surrogate as S
+
+    net = S.Network.load(weights)
+    wl = net.cfg.d_in == 5
+    errs, inside = S.curve_errors(net, cases, traj, wl)
+    X, _, _, _ = S.dataset(cases, traj, wl)
+    net.predict(X)                        # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        net.predict(X)
+    sur_s = (time.perf_counter() - t0) / reps
+    net.close()
+    ok = np.isfinite(errs[:, 0])
+    within = float(np.mean(errs[ok, 0] <= 1.0)) if ok.any() else 0.0
+    sur_pph = len(cases) * 3600.0 / sur_s
+    lbm_pph = len(cases) * 3600.0 / lbm_wall
+    return {"inputs": int(net.cfg.d_in), "surrogate_points_per_hour": round(sur_pph, 1),
+            "lbm_points_per_hour": round(lbm_pph, 1), "speedup": round(sur_pph / lbm_pph, 1),
+            "scored_channels": int(ok.sum()), "fraction_within_1lu": round(within, 4),
+            "points_per_hour_within_1lu": round(sur_pph * within, 1),
+            "max_dz_lu": round(float(np.nanmax(errs[:, 0])), 4),
+            "median_max_dz_lu": round(float(np.nanmedian(errs[:, 0])), 4),
+            "inside_training_hull": round(inside, 4), "samples_per_point": int(traj.shape[1])}
+
+
+def sweep_summary(sw: dict, steps: int) -> dict:
+    n = len(sw["cases"])
+    return {"channels": n, "steps": steps, "nodes": sw["cells"], "sample_every": 100,
+            "points_per_hour": round(n * 3600.0 / sw["wall"], 1),
+            "stable_points_per_hour": round((n - sw["unstable"]) * 3600.0 / sw["wall"], 1),
+            "unstable_channels": sw["unstable"], "wall_s": round(sw["wall"], 3),
+            "aggregate_mlups": round(sw["cells"] * steps / sw["wall"] / 1e6, 1),
+            "schedule": sw["schedule"]}
+
+
+def sweep(args) -> int:
+    steps = args.steps if args.steps != 10000 else 50_000
+    sw = run_sweep(steps, args.tile)
+    cells, tile = sw["cells"], sw["schedule"]
+    step_s = sw["event_step_s"]
+    launch_s = step_s * tile["fuse"]
+    # algorithmic bytes of one launch: 144 B per node (one read and one write of both population
+    # sets), whether it advances one step or two
+    achieved = 144 * cells / launch_s / 1e9
+    summ = sweep_summary(sw, steps)
     line = {
         "metric": "calibration-sweep points/hour, batched LBM (one point = one channel trajectory)",
-        "value": round(len(cases) * 3600.0 / wall, 1), "unit": "points/h", "n_gpus": 1,
-        "stable_points_per_hour": round((len(cases) - unstable) * 3600.0 / wall, 1),
-        "steps": steps, "warmup": 0, "ms_per_step": round(wall * 1e3 / steps, 5),
+        "value": summ["points_per_hour"], "unit": "points/h", "n_gpus": 1,
+        "stable_points_per_hour": summ["stable_points_per_hour"],
+        "steps": steps, "warmup": 0, "ms_per_step": round(sw["wall"] * 1e3 / steps, 5),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "sweep_64_channels", "channels": len(cases), "nodes": cells,
-                   "sample_every": every, "samples_recorded": ns, "schedule": tile,
-                   "aggregate_mlups": round(cells * steps / wall / 1e6, 1),
-                   "unstable_channels": unstable},
+        "config": {"workload": "sweep_64_channels", "channels": len(sw["cases"]), "nodes": cells,
+                   "sample_every": 100, "samples_recorded": sw["samples"], "schedule": tile,
+                   "aggregate_mlups": summ["aggregate_mlups"], "unstable_channels": sw["unstable"]},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                      "kernel": kernel_name(tile["fuse"]) + " (all channels per launch) + observation every 100 steps",
-                     "bytes_per_node_update": 144, "steps_per_launch": tile["fuse"]},
+                     "bytes_per_node_per_launch": 144, "steps_per_launch": tile["fuse"],
+                     "single_step_equiv_gbs": round(144 * cells / step_s / 1e9, 1)},
     }
     print(json.dumps(line), flush=True)
     return 0
@@ -457,6 +531,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--variant", choices=["fused", "two_kernel"], default="fused")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-sweep", action="store_true",
+                    help="roofline workload: leave out the sweep and surrogate sub-objects")
     ap.add_argument("--calibrate-copy", action="store_true")
     ap.add_argument("--tile", type=int, nargs="+", default=None, metavar="N",
                     help="BX CY ORDER [FUSE]: fixed schedule instead of the autotuner")
@@ -530,8 +606,10 @@ def main() -> int:
     step_s = ev_ms / 1e3 / args.steps
     launch_s = step_s * fuse                   # one launch advances `fuse` steps
     bpl = BYTES_PER_LUP[args.variant]
-    # algorithmic bytes per launch: bpl per node update x the node updates of one launch
-    achieved = bpl * cells * fuse / launch_s / 1e9
+    # algorithmic bytes of one launch: 144 B per node for the fused kernels (one read and one
+    # write of both population sets, for one step or two), 232 B per node for the two-kernel step
+    achieved = bpl * cells / launch_s / 1e9
+    single_equiv = bpl * cells * fuse / launch_s / 1e9
     if args.variant == "fused":
         traffic = measured_traffic(cells, tile)
     else:
@@ -547,14 +625,25 @@ def main() -> int:
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "kernel": kernel_name(fuse) if args.variant == "fused" else "k_density+k_collide",
-                     "bytes_per_node_update": bpl, "steps_per_launch": fuse,
+                     "bytes_per_node_per_launch": bpl, "steps_per_launch": fuse,
                      "event_ms_per_launch": round(launch_s * 1e3, 5),
+                     # the same launch priced per node update (two steps share one read and one
+                     # write, so this can pass the HBM peak)
+                     "single_step_equiv_gbs": round(single_equiv, 1),
                      "traffic_gbs": round(traffic / launch_s / 1e9, 1) if traffic else None,
-                     # measured HBM bytes per second over the peak (two steps per launch share
-                     # one read and one write, so `frac` can pass 1 while this cannot)
                      "traffic_frac": round(traffic / launch_s / 1e9 / HBM_PEAK_GBS, 4) if traffic else None},
         "health": {"flags": obs["flags"], "z": obs["z"], "mass": list(obs["mass"])},
     }
+    if not args.no_sweep:
+        # the calibration sweep and the surrogate scored on its trajectories (the second half of
+        # the metric), after the roofline channel's memory is released
+        ch.close()
+        del ch
+        torch.cuda.empty_cache()
+        sw_steps = 50_000
+        sw = run_sweep(sw_steps)
+        line["sweep"] = sweep_summary(sw, sw_steps)
+        line["surrogate"] = score_surrogate(args.weights, sw["cases"], sw["traj"], sw["wall"])
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(case)
     print(json.dumps(line), flush=True)

@@ -127,7 +127,9 @@ int scf_init(scf_ctx** out, const scf_geometry* geom, const scf_params* params,
 /* Advance nsteps >= 0 time steps of eq. lbe: densities, forces (eqs. forcing, forcingw),
  * common velocity, shifted equilibrium, BGK collision, streaming with half-way bounce-back.
  * Asynchronous on the stream; launches are replayed from a captured HIP graph when nsteps is
- * large enough.  Errors: SCF_EINVAL, SCF_EDEVICE (launch failure). */
+ * large enough.  Errors: SCF_EINVAL, SCF_EDEVICE (launch failure), SCF_EUNSTABLE (reported
+ * lazily: the last scf_observe found flags bit1 set; the steps were still enqueued, and no
+ * synchronisation is added to find out). */
 int scf_step(scf_ctx* ctx, int64_t nsteps);
 
 /* Observables of the current state (see scf_obs).  Enqueues two small kernels, copies one
@@ -193,7 +195,9 @@ int scf_batch_init(scf_batch** out, int32_t nchan, const scf_geometry* geoms,
                    int32_t sample_every, int32_t max_samples, void* dev_ws, size_t ws_bytes,
                    void* hip_stream);
 
-/* Advance every channel by nsteps, recording samples on the way.  Asynchronous. */
+/* Advance every channel by nsteps, recording samples on the way.  Asynchronous.  Returns
+ * SCF_EUNSTABLE (after enqueueing the steps) when the last scf_batch_observe found an unstable
+ * sample. */
 int scf_batch_step(scf_batch* b, int64_t nsteps);
 
 /* Copy the recorded samples to out[c * max_samples + s] (nchan * max_samples records) and the
@@ -326,7 +330,7 @@ int scf3_init(scf3_ctx** out, const scf3_geometry* geom, const scf_params* param
               void* hip_stream);
 
 /* Advance nsteps >= 0 steps (one launch each, two in the two-kernel form; asynchronous on the
- * stream). */
+ * stream).  SCF_EUNSTABLE (after enqueueing) when the last scf3_observe found flags bit1 set. */
 int scf3_step(scf3_ctx* ctx, int64_t nsteps);
 
 /* Step schedule: fused = 1 (one kernel, cy >= 1 rows of y per tile, default 16 or the two-kernel

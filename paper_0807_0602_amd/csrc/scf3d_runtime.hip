@@ -70,6 +70,7 @@ struct scf3_ctx {
     int cur = 0;
     int64_t t = 0;
     int fused = 1, cy = 16;
+    int32_t seen_flags = 0;   // flags of the last scf3_observe (see scf3_step)
     float* base() const { return reinterpret_cast<float*>(ws); }
     scf3::Chan3* d_chan() const { return reinterpret_cast<scf3::Chan3*>(ws + lay.chan); }
 };
@@ -148,6 +149,9 @@ int scf3_step(scf3_ctx* c, int64_t nsteps) {
         c->cur ^= 1;
         c->t += 1;
     }
+    if (c->seen_flags & 2)
+        return fail(SCF_EUNSTABLE, "the last observation found a non-finite or negative density "
+                                   "(the steps were still enqueued)");
     return SCF_OK;
 }
 
@@ -180,6 +184,7 @@ int scf3_observe(scf3_ctx* c, scf3_obs* out) {
     static_assert(sizeof(scf3::Obs3) == sizeof(scf3_obs), "record layout");
     std::memcpy(out, &r, sizeof r);
     out->t = c->t;
+    c->seen_flags = out->flags;
     if (out->flags & 2) return fail(SCF_EUNSTABLE, "non-finite or negative density in the state");
     return SCF_OK;
 }

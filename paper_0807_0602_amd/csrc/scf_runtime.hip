@@ -170,6 +170,9 @@ struct Engine {
     int sample_every = 0, max_samples = 1;
     int64_t recorded = 0;
     bool batch = false;
+    // flags of the last observation copied to the host (scf_observe, scf_batch_observe); a
+    // later step reports bit 1 as SCF_EUNSTABLE without synchronising
+    int32_t seen_flags = 0;
 
     scf::Chan* d_chans() const { return reinterpret_cast<scf::Chan*>(ws + lay.chans); }
     scf::RowRef* d_rows() const { return reinterpret_cast<scf::RowRef*>(ws + lay.rows); }
@@ -564,9 +567,18 @@ int scf_init(scf_ctx** out, const scf_geometry* geom, const scf_params* params, 
     return SCF_OK;
 }
 
+// Instability found by the last observation, reported after the steps were enqueued.
+static int lazy_unstable(const Engine& e) {
+    if (e.seen_flags & 2)
+        return fail(SCF_EUNSTABLE, "the last observation found a non-finite or negative density "
+                                   "(the steps were still enqueued)");
+    return SCF_OK;
+}
+
 int scf_step(scf_ctx* ctx, int64_t nsteps) {
     if (!ctx || nsteps < 0) return fail(SCF_EINVAL, "bad context or negative step count");
-    return ctx->e.advance(nsteps);
+    int rc = ctx->e.advance(nsteps);
+    return rc ? rc : lazy_unstable(ctx->e);
 }
 
 int scf_observe(scf_ctx* ctx, scf_obs* out) {
@@ -579,6 +591,7 @@ int scf_observe(scf_ctx* ctx, scf_obs* out) {
     static_assert(sizeof(scf::ObsRec) == sizeof(scf_obs), "record layout");
     std::memcpy(out, &r, sizeof r);
     out->t = e.t;
+    e.seen_flags = out->flags;
     if (out->flags & 2) return fail(SCF_EUNSTABLE, "non-finite or negative density in the state");
     return SCF_OK;
 }
@@ -736,7 +749,8 @@ int scf_batch_init(scf_batch** out, int32_t nchan, const scf_geometry* geoms, co
 
 int scf_batch_step(scf_batch* b, int64_t nsteps) {
     if (!b || nsteps < 0) return fail(SCF_EINVAL, "bad batch or negative step count");
-    return b->e.advance_sampled(nsteps);
+    int rc = b->e.advance_sampled(nsteps);
+    return rc ? rc : lazy_unstable(b->e);
 }
 
 int scf_batch_observe(scf_batch* b, scf_obs* out, int64_t* nsamples) {
@@ -761,6 +775,7 @@ int scf_batch_observe(scf_batch* b, scf_obs* out, int64_t* nsamples) {
             }
         }
     *nsamples = have;
+    e.seen_flags = unstable ? 2 : 0;
     if (unstable) return fail(SCF_EUNSTABLE, "a recorded sample holds a non-finite or negative density");
     return SCF_OK;
 }

@@ -95,8 +95,9 @@ class Channel:
     def t(self) -> int:
         return int(L.scf_time(self._h))
 
-    def step(self, n: int = 1) -> "Channel":
-        L.check(L.scf_step(self._h, int(n)))
+    def step(self, n: int = 1, allow_unstable: bool = False) -> "Channel":
+        # SCF_EUNSTABLE here is the last observation's flag, reported after the steps were enqueued
+        L.check(L.scf_step(self._h, int(n)), allow=(L.SCF_EUNSTABLE,) if allow_unstable else ())
         return self
 
     def observe(self, allow_unstable: bool = False) -> dict:
@@ -182,8 +183,8 @@ class Batch:
     def __del__(self):
         self.close()
 
-    def step(self, n: int) -> "Batch":
-        L.check(L.scf_batch_step(self._h, int(n)))
+    def step(self, n: int, allow_unstable: bool = False) -> "Batch":
+        L.check(L.scf_batch_step(self._h, int(n)), allow=(L.SCF_EUNSTABLE,) if allow_unstable else ())
         return self
 
     def observe(self, allow_unstable: bool = False):
@@ -254,8 +255,8 @@ class Channel3:
     def t(self) -> int:
         return int(L.scf3_time(self._h))
 
-    def step(self, n: int = 1) -> "Channel3":
-        L.check(L.scf3_step(self._h, int(n)))
+    def step(self, n: int = 1, allow_unstable: bool = False) -> "Channel3":
+        L.check(L.scf3_step(self._h, int(n)), allow=(L.SCF_EUNSTABLE,) if allow_unstable else ())
         return self
 
     def set_schedule(self, fused: bool = True, cy: int = 16) -> "Channel3":

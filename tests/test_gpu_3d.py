@@ -12,6 +12,7 @@ import pytest
 
 import oracle
 from paper_0807_0602_amd import inputs
+from parity_util import front_diff, max_abs_diff
 
 pytestmark = pytest.mark.gpu
 
@@ -76,14 +77,13 @@ def test_density_front_mass_300_steps(S, name, g, gw, tau):
             ch.step(50)
             o.step(50)
         a, b = ch.observe(), o.observe()
-        if np.isfinite(b["z"]):
-            worst_z = max(worst_z, abs(a["z"] - b["z"]))
+        worst_z = max(worst_z, front_diff(a["z"], b["z"]))
         for k in range(2):
             assert abs(a["mass"][k] - b["mass"][k]) / b["mass"][k] < 1e-5
         assert not a["flags"] & 2
     nA, nB = ch.density()
     rA, rB = o.density()
-    err = max(np.abs(nA - rA).max(), np.abs(nB - rB).max())
+    err = max_abs_diff((nA, rA), (nB, rB))
     _say(f"  {name}: max|drho| = {err:.2e} max|dz| = {worst_z:.2e}")
     assert err <= 1e-5 and worst_z <= 0.5
 
@@ -99,10 +99,10 @@ def test_z_invariant_slit_is_the_2d_channel(S):
     c2.step(200)
     nA3, nB3 = c3.density()
     nA2, nB2 = c2.density()
-    err = max(np.abs(nA3 - nA2[None]).max(), np.abs(nB3 - nB2[None]).max())
+    err = max_abs_diff((nA3, np.broadcast_to(nA2[None], nA3.shape)), (nB3, np.broadcast_to(nB2[None], nB3.shape)))
     _say(f"  z-invariant slit vs 2-D channel after 200 steps: max|drho| = {err:.2e}")
     assert err <= 2e-6
-    assert abs(c3.observe()["z"] - c2.observe()["z"]) <= 1e-3
+    assert front_diff(c3.observe()["z"], c2.observe()["z"]) <= 1e-3
 
 
 def test_wetting_duct_fills(S):
@@ -183,7 +183,7 @@ def test_health_flag_follows_the_oracle(S, tau):
     _say(f"case: 3-D health flag, tau={tau}")
     flags = []
     for t in range(1, 13):
-        ch.step(1)
+        ch.step(1, allow_unstable=True)
         o.step(1)
         gpu_bad = bool(ch.observe(allow_unstable=True)["flags"] & 2)
         nA, nB = o.density()

@@ -12,6 +12,7 @@ import numpy as np
 import pytest
 
 import oracle
+from parity_util import front_diff, max_abs_diff
 from paper_0807_0602_amd import inputs
 
 pytestmark = pytest.mark.gpu
@@ -98,10 +99,10 @@ def test_fuse2_parity_with_oracle(scf):
             ch.step(100)
             orc.step(100)
         g, r = ch.observe(), orc.observe()
-        worst_z = max(worst_z, abs(g["z"] - r["z"]))
+        worst_z = max(worst_z, front_diff(g["z"], r["z"]))
     nA, nB = ch.density()
     rA, rB = orc.density()
-    err = max(np.abs(nA - rA).max(), np.abs(nB - rB).max())
+    err = max_abs_diff((nA, rA), (nB, rB))
     _say(f"  max|drho| = {err:.3e}  max|dz| = {worst_z:.3e}")
     assert err <= 1e-5 and worst_z <= 0.5
 

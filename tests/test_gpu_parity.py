@@ -14,6 +14,7 @@ import pytest
 
 import oracle
 from paper_0807_0602_amd import inputs
+from parity_util import front_diff, max_abs_diff
 
 pytestmark = pytest.mark.gpu
 
@@ -60,7 +61,7 @@ def test_density_parity_1000_steps(scf, seed):
     ch.step(1000)
     nA, nB = ch.density()
     rA, rB = _oracle_run(case, 1000).density()
-    err = max(np.abs(nA - rA).max(), np.abs(nB - rB).max())
+    err = max_abs_diff((nA, rA), (nB, rB))
     _say(f"  max|drho| = {err:.3e}")
     assert err <= RHO_TOL
 
@@ -78,8 +79,8 @@ def test_front_and_mass_through_2000_steps(scf):
             orc.step(10)
         g, r = ch.observe(), orc.observe()
         assert g["t"] == r["t"] == t
-        worst_z = max(worst_z, abs(g["z"] - r["z"]))
-        worst_p = max(worst_p, abs(g["precursor"] - r["precursor"]))
+        worst_z = max(worst_z, front_diff(g["z"], r["z"]))
+        worst_p = max(worst_p, front_diff(g["precursor"], r["precursor"]))
         assert g["flags"] == r["flags"]
         for k in range(2):
             assert abs(g["mass"][k] - r["mass"][k]) / r["mass"][k] < 1e-5
@@ -203,7 +204,8 @@ def test_rejects_tau_at_one_half(scf):
 
 def test_instability_is_flagged(scf):
     """tau_B = 0.55 with tau_A = 1 goes unstable on the 200 x 24 capillary: both the oracle and
-    the GPU must report it (health flag bit 1, SCF_EUNSTABLE)."""
+    the GPU must report it (health flag bit 1, SCF_EUNSTABLE), and after that observation the
+    next scf_step reports it too (lazily, after enqueueing its steps)."""
     from paper_0807_0602_amd import _lib as L
     case = inputs.with_params(inputs.capillary_small(seed=1), tau=(1.0, 0.55))
     _say("case: instability flag, tau = (1.0, 0.55)")
@@ -212,7 +214,12 @@ def test_instability_is_flagged(scf):
     t_orc = t_gpu = None
     for t in range(100, 3001, 100):
         orc.step(100)
-        ch.step(100)
+        if t_gpu is None:
+            ch.step(100)                  # no observation has found instability yet
+        else:
+            with pytest.raises(L.ScfError) as e:
+                ch.step(100)
+            assert e.value.code == L.SCF_EUNSTABLE
         if t_orc is None and orc.observe()["flags"] & 2:
             t_orc = t
         if t_gpu is None:
@@ -268,13 +275,12 @@ def test_batch_against_oracle(scf):
         orc = oracle.Oracle.from_case(case).init(*case.fields())
         for s in range(ns):
             r, o = recs[c][s], orc.observe()
-            if not (math.isnan(r["z"]) and math.isnan(o["z"])):
-                assert abs(r["z"] - o["z"]) <= Z_TOL
+            assert front_diff(r["z"], o["z"]) <= Z_TOL
             orc.step(100)
         nA, nB = b.density(c)
         orc2 = oracle.Oracle.from_case(case).init(*case.fields()).step(500)
         rA, rB = orc2.density()
-        assert max(np.abs(nA - rA).max(), np.abs(nB - rB).max()) <= RHO_TOL
+        assert max_abs_diff((nA, rA), (nB, rB)) <= RHO_TOL
 
 
 # ------------------------------------------------------------------------------ full sizes
@@ -297,6 +303,7 @@ def _window_check(scf, case, T, centres, half, tile=BENCH_TILE):
 def _windows_of(case, nA, nB, T, centres, half):
     """Largest density difference between the GPU fields (nA, nB after T steps) and the oracle
     run on windows around the given columns (see _window_check)."""
+    assert np.isfinite(nA).all() and np.isfinite(nB).all(), "non-finite GPU density"
     worst = 0.0
     nx = case.geom.nx
     for xc in centres:
@@ -307,7 +314,7 @@ def _windows_of(case, nA, nB, T, centres, half):
         rA, rB = orc.density()
         inner = np.arange(2 * T + 1, w - 2 * T - 1)
         cols = (xa + inner) % nx
-        worst = max(worst, np.abs(nA[:, cols] - rA[:, inner]).max(), np.abs(nB[:, cols] - rB[:, inner]).max())
+        worst = max(worst, max_abs_diff((nA[:, cols], rA[:, inner]), (nB[:, cols], rB[:, inner])))
     return worst
 
 

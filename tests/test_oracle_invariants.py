@@ -1,8 +1,9 @@
 """Invariants the paper's set-up fixes (Sec. 2-3).
 
 P4: per-component mass is conserved (periodic box, bounce-back walls).
-P5: with no walls the total momentum is conserved, because the pair force of eq. forcing is
-    antisymmetric in (x, x') and the common velocity U conserves momentum at collision.
+P5: with no walls the total momentum sum_k m_k sum_i c_i f_i is conserved, because the pair
+    force of eq. forcing is antisymmetric in (x, x') and the common velocity U conserves
+    momentum at collision (also with unequal molecular masses m_k).
 P6: the capillary is mirror-symmetric about its centre line, so is a noise-free solution.
 Translation: a periodic shift of a wall-free initial state shifts the solution exactly.
 """
@@ -53,6 +54,34 @@ def test_momentum_conservation_without_walls():
     for _ in range(4):
         o.step(50)
         np.testing.assert_allclose(momentum(), p0, rtol=0, atol=1e-12)
+
+
+def test_mass_weighted_momentum_conservation_unequal_masses():
+    """P5 with molecular masses m = (1, 1.5) and tau = (1, 0.8): rho_k u_k = m_k j_k, and the
+    collision conserves sum_k m_k j_k up to the total force, whose sum over a wall-free box
+    vanishes.  A mass factor dropped from the common velocity U or from u^eq = U + tau F / rho
+    breaks the conservation; the unweighted sum sum_k j_k is not conserved."""
+    rng = np.random.default_rng(12)
+    nx, ny = 24, 16
+    m = (1.0, 1.5)
+    f = rng.uniform(0.02, 0.25, size=(2, 9, ny, nx))
+    o = oracle.Oracle(nx, ny, 0, 0, G=0.9, tau=(1.0, 0.8), alpha=(4 / 9, 0.6), mass=m)
+    o.set_populations(f)
+
+    def momenta():
+        g = o.populations()
+        jk = np.array([[np.einsum("iyx,i->", g[k], CX), np.einsum("iyx,i->", g[k], CY)] for k in range(2)])
+        return m[0] * jk[0] + m[1] * jk[1], jk[0] + jk[1]
+
+    p0, q0 = momenta()
+    assert np.abs(p0).max() > 0.1
+    drift = 0.0
+    for _ in range(4):
+        o.step(50)
+        p, q = momenta()
+        np.testing.assert_allclose(p, p0, rtol=0, atol=1e-12)
+        drift = max(drift, float(np.abs(q - q0).max()))
+    assert drift > 1e-4           # the unweighted momentum does move: the masses matter
 
 
 def test_mirror_symmetry_capillary():

@@ -59,6 +59,36 @@ def test_unequal_sound_speeds_flat_interface():
     assert abs(p(la, lb, eq) - p(ga, gb, eq)) > 0.05 * p(la, lb, eq)
 
 
+def test_unequal_masses_flat_interface():
+    """Components of unequal molecular mass (rho_k = m_k n_k, Sec. 2; m = (1, 1.5)) across a
+    flat interface at rest: the momentum flux of component k is m_k n_k c_s^2 while the forces of
+    eq. forcing act on the number densities, so mechanical equilibrium holds for
+    p = sum_k m_k n_k / 3 + (G/3) n_A n_B, and not for the mass-blind sum_k n_k / 3 + (G/3) n_A n_B.
+    The mixture velocity (the mass-weighted mean plus half the force per density) vanishes."""
+    nx, ny, G = 128, 4, 0.9
+    m = (1.0, 1.5)
+    X = np.arange(nx)[None, :].repeat(ny, 0)
+    liq = (X >= 32) & (X < 96)
+    a = np.where(liq, 2.0, 0.06) * m[0]       # init takes rho_k = m_k n_k
+    b = np.where(liq, 0.06, 2.0) * m[1]
+    oracle.set_threads(8)
+    o = oracle.Oracle(nx, ny, 0, 0, G, (0.0, 0.0), (1.0, 1.0), mass=m).init(a, b)
+    o.step(40000)   # the pressure difference decays to 4e-8 (7e-11 by 80 000 steps)
+    A, B = o.density()
+    la, lb, ga, gb = A[0, 64], B[0, 64], A[0, 0], B[0, 0]
+    assert la > 1.5 and gb > 1.0 and lb < 0.2 and ga < 0.2
+
+    def p(nA, nB, mm):
+        return mm[0] * nA / 3 + mm[1] * nB / 3 + G / 3 * nA * nB
+
+    assert abs(p(la, lb, m) - p(ga, gb, m)) <= 1e-6 * p(la, lb, m)
+    assert abs(p(la, lb, (1, 1)) - p(ga, gb, (1, 1))) > 1e-2 * p(la, lb, (1, 1))
+    mac = o.macro()
+    rho = m[0] * mac["n"][0] + m[1] * mac["n"][1]
+    u = (m[0] * mac["j"][0] + m[1] * mac["j"][1] + 0.5 * (mac["F"][0] + mac["F"][1])) / rho[None]
+    assert np.abs(u).max() <= 1e-6
+
+
 def test_laplace_law():
     n = 96
     rows = []
