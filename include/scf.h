@@ -282,6 +282,22 @@ int scf_sur_train(scf_sur* s, int64_t steps, int32_t batch, float* last_loss);
  * the LBM. */
 int scf_sur_predict(scf_sur* s, const float* X, int64_t n, float* Y, uint8_t* in_hull);
 
+/* Allocation-free form of scf_sur_predict, for callers that cannot allocate device memory or
+ * synchronise: code under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation.  X (n*d_in floats), Y (n*2 floats) and in_hull (optional, n bytes: 1 where every
+ * input lies inside the training hull, all 0 before any data or norm was set) are DEVICE
+ * pointers owned by the caller.  The same layer kernels as scf_sur_predict give the same Y bit
+ * for bit.  Their activations live in a library-owned device array of 20 MiB per GPU (held
+ * until the process ends) instead of the workspace; one call takes rows_pad * (4 d_in +
+ * 16 width) bytes of it (rows_pad = n rounded up to 64, plus alignment), so at width 256 and 5
+ * inputs up to 5056 rows per call; larger n returns SCF_EINVAL and nothing is enqueued.
+ * Asynchronous on the network's stream; no allocation, copy to or from the host, or
+ * synchronisation.  The array keeps the last call's contents; every call writes the parts it
+ * reads.  Calls that overlap on one GPU (any networks, any streams) race on the array.  Errors:
+ * SCF_EINVAL (NULL, n < 0, n too large), SCF_EDEVICE (launch failure, or no array address on
+ * the device current at scf_sur_create). */
+int scf_sur_predict_noalloc(scf_sur* s, const float* X, int64_t n, float* Y, uint8_t* in_hull);
+
 void scf_sur_destroy(scf_sur* s);
 
 /* ---------------------------------------------------------------------------------------------

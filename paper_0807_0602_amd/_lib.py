@@ -127,6 +127,7 @@ _sig = {
     "scf_sur_step": (C.c_int, [_vp, _fp, _fp, _fp, C.c_int32, _fp]),
     "scf_sur_train": (C.c_int, [_vp, C.c_int64, C.c_int32, _fp]),
     "scf_sur_predict": (C.c_int, [_vp, _fp, C.c_int64, _fp, C.POINTER(C.c_uint8)]),
+    "scf_sur_predict_noalloc": (C.c_int, [_vp, _vp, C.c_int64, _vp, _vp]),
     "scf_sur_destroy": (None, [_vp]),
     "scf3_workspace_bytes": (C.c_size_t, [C.POINTER(scf3_geometry)]),
     "scf3_init": (C.c_int, [C.POINTER(_vp), C.POINTER(scf3_geometry), C.POINTER(scf_params), _dp, _dp,

@@ -38,6 +38,10 @@ hipError_t gather(const float* X, const float* T, const float* w, int64_t src_ro
                   uint64_t seed, const int64_t* step, hipStream_t s);
 hipError_t hull(const float* X, int d_in, int rows, const float* lo, const float* hi, uint8_t* in,
                 hipStream_t s);
+// Rows i < n of X normalised by (mean, stdv) into Xn (rows >= n entries, padding rows zeroed).
+hipError_t normalise(const float* X, int64_t n, int d_in, int rows, const float* mean, const float* stdv,
+                     float* Xn, hipStream_t s);
+hipError_t fill_u8(uint8_t* p, int64_t n, uint8_t v, hipStream_t s);
 hipError_t init_params(float* theta, int64_t off, int n_out, int n_in, uint64_t seed, hipStream_t s);
 
 }  // namespace sur

@@ -375,6 +375,22 @@ k_gather(const float* __restrict__ X, const float* __restrict__ T, const float* 
     }
 }
 
+// Rows i < n of X (caller's device memory) normalised into Xn as k_gather does; padding rows
+// [n, rows) are set to 0 (rows are independent through the network and their outputs unused).
+__global__ void __launch_bounds__(kThreads)
+k_normalise(const float* __restrict__ X, int64_t n, int d_in, int rows, const float* __restrict__ mean,
+            const float* __restrict__ stdv, float* __restrict__ Xn) {
+    const int i = blockIdx.x * kThreads + threadIdx.x;
+    if (i >= rows) return;
+    for (int k = 0; k < d_in; ++k)
+        Xn[(int64_t)i * d_in + k] = i < n ? (X[(int64_t)i * d_in + k] - mean[k]) / stdv[k] : 0.0f;
+}
+
+__global__ void __launch_bounds__(kThreads) k_fill_u8(uint8_t* __restrict__ p, int64_t n, uint8_t v) {
+    const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
 // Inputs inside the axis-aligned box of the stored training inputs.
 __global__ void __launch_bounds__(kThreads)
 k_hull(const float* __restrict__ X, int d_in, int rows, const float* __restrict__ lo,
@@ -502,6 +518,17 @@ hipError_t gather(const float* X, const float* T, const float* w, int64_t src_ro
 hipError_t hull(const float* X, int d_in, int rows, const float* lo, const float* hi, uint8_t* in,
                 hipStream_t s) {
     hipLaunchKernelGGL(k_hull, grid1(rows), dim3(kThreads), 0, s, X, d_in, rows, lo, hi, in);
+    return hipGetLastError();
+}
+
+hipError_t normalise(const float* X, int64_t n, int d_in, int rows, const float* mean, const float* stdv,
+                     float* Xn, hipStream_t s) {
+    hipLaunchKernelGGL(k_normalise, grid1(rows), dim3(kThreads), 0, s, X, n, d_in, rows, mean, stdv, Xn);
+    return hipGetLastError();
+}
+
+hipError_t fill_u8(uint8_t* p, int64_t n, uint8_t v, hipStream_t s) {
+    hipLaunchKernelGGL(k_fill_u8, grid1(n), dim3(kThreads), 0, s, p, n, v);
     return hipGetLastError();
 }
 

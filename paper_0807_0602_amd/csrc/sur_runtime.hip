@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -29,6 +30,40 @@ using scf::set_error;
     } while (0)
 
 size_t al(size_t v) { return (v + 255) / 256 * 256; }
+
+// ---------------------------------------------------------------------------------------------
+// Scratch of the allocation-free prediction (scf_sur_predict_noalloc): the normalised inputs and
+// two layers of activations of one call, carved as in noalloc_bytes.  A device array: each GPU
+// the library runs on holds its own copy until the process ends.  Host code never passes the
+// array's name to a kernel or a copy (on the host it is only a stand-in); it uses the per-device
+// address that scratch_address fetches with hipGetSymbolAddress, once per device, at
+// scf_sur_create with that device current.
+// ---------------------------------------------------------------------------------------------
+constexpr size_t kNoAllocScratchBytes = (size_t)20 << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_at[kMaxDevices] = {};
+
+hipError_t scratch_address(int dev, void** out) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_at[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_at[dev] = p;
+    }
+    *out = g_scratch_at[dev];
+    return hipSuccess;
+}
+
+// Scratch bytes of a prediction over `rows` (a multiple of 64) rows: normalised inputs, then
+// two (FP32 pre-activation, BF16 activation, BF16 transposed activation) layer slots.
+size_t noalloc_bytes(int64_t rows, int d_in, int width) {
+    const size_t r = (size_t)rows, w = (size_t)width;
+    return al(4 * r * d_in) + 2 * (al(4 * r * w) + 2 * al(2 * r * w));
+}
 
 struct Plan {
     size_t total = 0;
@@ -116,6 +151,8 @@ struct scf_sur {
     bool have_stats = false;
     hipGraphExec_t train_graph = nullptr;
     int train_rows = 0;
+    void* scratch_dev = nullptr;     // this device's address of `scratch` (NULL: see scratch_err)
+    std::string scratch_err;
 
     template <class T>
     T* at(size_t off) const { return reinterpret_cast<T*>(ws + off); }
@@ -247,6 +284,21 @@ int scf_sur_create(scf_sur** out, const scf_sur_cfg* cfg, void* dev_ws, size_t w
     if (e == hipSuccess) e = s->shadows(st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) return fail("surrogate initialisation", e);
+    // address of the allocation-free prediction's scratch on the current device (the one that
+    // holds the workspace); a failure only disables scf_sur_predict_noalloc
+    int dev = -1;
+    e = hipGetDevice(&dev);
+    if (e != hipSuccess) {
+        s->scratch_err = std::string("hipGetDevice: ") + hipGetErrorString(e);
+    } else if (dev < 0 || dev >= kMaxDevices) {
+        s->scratch_err = "device index " + std::to_string(dev) + " beyond the scratch table";
+    } else {
+        e = scratch_address(dev, &s->scratch_dev);
+        if (e != hipSuccess) {
+            s->scratch_dev = nullptr;
+            s->scratch_err = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+        }
+    }
     *out = s;
     return SCF_OK;
 }
@@ -415,6 +467,54 @@ int scf_sur_predict(scf_sur* s, const float* X, int64_t n, float* Y, uint8_t* in
     }
     if (in_hull && !s->have_stats)
         for (int64_t i = 0; i < n; ++i) in_hull[i] = 0;
+    return SCF_OK;
+}
+
+int scf_sur_predict_noalloc(scf_sur* s, const float* X, int64_t n, float* Y, uint8_t* in_hull) {
+    if (!s) return set_error(SCF_EINVAL, "NULL network");
+    if (n < 0) return set_error(SCF_EINVAL, "negative row count");
+    if (n == 0) return SCF_OK;
+    if (!X || !Y) return set_error(SCF_EINVAL, "NULL input or output");
+    const int din = s->cfg.d_in, Wd = s->cfg.width, D = s->cfg.depth;
+    const int64_t rows = (n + 63) / 64 * 64;
+    if (rows > (1 << 30) || noalloc_bytes(rows, din, Wd) > kNoAllocScratchBytes)
+        return set_error(SCF_EINVAL, std::to_string(n) + " rows need " +
+                                         std::to_string(noalloc_bytes(std::min<int64_t>(rows, 1 << 30), din, Wd)) +
+                                         " bytes of scratch; the allocation-free prediction has " +
+                                         std::to_string(kNoAllocScratchBytes) + " (split the rows over calls)");
+    if (!s->scratch_dev) return set_error(SCF_EDEVICE, "no scratch on this device: " + s->scratch_err);
+    char* base = static_cast<char*>(s->scratch_dev);
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        char* p = base + off;
+        off = al(off + bytes);
+        return p;
+    };
+    float* Xn = reinterpret_cast<float*>(take(4 * (size_t)rows * din));
+    float* Z[2];
+    __bf16* H[2];
+    __bf16* HT[2];
+    for (int q = 0; q < 2; ++q) {
+        Z[q] = reinterpret_cast<float*>(take(4 * (size_t)rows * Wd));
+        H[q] = reinterpret_cast<__bf16*>(take(2 * (size_t)rows * Wd));
+        HT[q] = reinterpret_cast<__bf16*>(take(2 * (size_t)rows * Wd));
+    }
+    hipStream_t st = s->stream;
+    // the same layer kernels as scf_sur_predict, activations alternating between two slots
+    SUR_TRY(scf::sur::normalise(X, n, din, (int)rows, s->at<float>(s->p.mean), s->at<float>(s->p.stdv), Xn, st));
+    SUR_TRY(scf::sur::first_forward(Xn, din, s->W(0), s->b(0), Wd, (int)rows, Z[0], H[0], HT[0], st));
+    for (int l = 1; l < D; ++l)
+        SUR_TRY(scf::sur::gemm_forward(H[(l - 1) & 1], s->Wb(l), s->b(l), (int)rows, Wd, Z[l & 1], H[l & 1],
+                                       HT[l & 1], st));
+    // output rows m < n straight into the caller's Y (inference: no targets)
+    SUR_TRY(scf::sur::output_layer(Z[(D - 1) & 1], Wd, (int)n, s->W(D), s->b(D), nullptr, nullptr, 1.0f, Y,
+                                   nullptr, nullptr, nullptr, nullptr, nullptr, st));
+    if (in_hull) {
+        if (s->have_stats)
+            SUR_TRY(scf::sur::hull(X, din, (int)n, s->at<float>(s->p.lo), s->at<float>(s->p.hi), in_hull, st));
+        else
+            SUR_TRY(scf::sur::fill_u8(in_hull, n, 0, st));
+    }
     return SCF_OK;
 }
 
