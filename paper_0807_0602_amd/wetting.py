@@ -156,6 +156,28 @@ def fit_circle(pts: np.ndarray) -> Tuple[float, float, float]:
     return float(xc), float(yc), float(np.sqrt(xc * xc + yc * yc - F))
 
 
+def meniscus_radius(nA: np.ndarray, nB: np.ndarray, x_front: float, H: int, skip: int = 0) -> Dict:
+    """Radius of curvature of a meniscus spanning a channel of H fluid rows (rows 1..H, walls on
+    rows 0 and H + 1): a circle fitted to the n_A = n_B contour points in the columns from
+    x_front - 4 to x_front + H (the meniscus and its contact-line region, x_front the centre-line
+    front) and the rows at least `skip` nodes from the wall rows.  Across a 2-D meniscus the
+    pressure jumps by gamma / R (Laplace), i.e. 2 gamma cos(theta) / H with cos(theta) = H / (2 R)
+    the apparent contact angle: the capillary pressure that drives the filling, moving or at rest."""
+    phi = np.asarray(nA, dtype=np.float64) - np.asarray(nB, dtype=np.float64)
+    x_lo = max(int(np.floor(x_front)) - 4, 0)
+    x_hi = min(int(np.ceil(x_front)) + H, phi.shape[1])
+    sub_ = phi[:H + 2, x_lo:x_hi].copy()
+    sub_[0, :] = sub_[H + 1, :] = np.nan          # wall rows hold no fluid
+    pts = _contour_points(np.nan_to_num(sub_, nan=0.0), 1 + skip)
+    if len(pts):
+        pts = pts[(pts[:, 1] >= 1 + skip) & (pts[:, 1] <= H - skip)]
+    if len(pts) < 8:
+        return {"R": float("nan"), "npts": int(len(pts))}
+    xc, yc, R = fit_circle(pts)
+    return {"R": R, "xc": xc + x_lo, "yc": yc, "npts": int(len(pts)),
+            "cos": float(H / (2.0 * R)) if R > 0 else float("nan")}
+
+
 def sessile_cos(cases: Sequence[WallCase], R: float = 24.0, nx: int = 160, ny: int = 72,
                 steps: int = 30000, skip: int = 4, rho: Pair = (2.0, 0.06),
                 gas: Optional[Pair] = None) -> List[Dict]:

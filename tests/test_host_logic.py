@@ -192,3 +192,20 @@ def test_bench_refuses_more_than_one_gpu():
                        text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr
+
+
+def test_meniscus_radius_of_a_synthetic_arc():
+    """A concave meniscus of radius 45 spanning H = 60 rows (centre of curvature on the gas side):
+    the circle fit recovers R and the apparent cos(theta) = H / (2 R)."""
+    from paper_0807_0602_amd import wetting
+    H, R, xc = 60, 45.0, 160.0
+    ny, nx = H + 2, 260
+    yc = (ny - 1) / 2.0
+    Y, X = np.meshgrid(np.arange(ny), np.arange(nx), indexing="ij")
+    d = np.hypot(X - xc, Y - yc)
+    phi = np.where(X < xc, np.tanh((d - R) / 2.0), -1.0)   # liquid (phi > 0) left of the arc
+    nA, nB = 1.0 + 0.5 * phi, 1.0 - 0.5 * phi
+    m = wetting.meniscus_radius(nA, nB, x_front=xc - R, H=H, skip=6)
+    assert m["npts"] > 30
+    assert abs(m["R"] - R) < 0.02 * R
+    assert abs(m["cos"] - H / (2 * R)) < 0.02

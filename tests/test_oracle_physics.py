@@ -176,3 +176,34 @@ def test_equal_viscosity_front_follows_eq_analy():
     s1 = np.polyfit(ts[(ts >= 3000) & (ts <= 4500)], zs[(ts >= 3000) & (ts <= 4500)], 1)[0]
     s2 = np.polyfit(ts[ts >= 4500], zs[ts >= 4500], 1)[0]
     assert abs(s1 / s2 - 1.0) < 0.03
+
+
+def test_precursor_lead_grows_only_in_complete_wetting():
+    """P12 at reduced size (400 x 22 capillary, channel x in [100, 380), 6000 steps): at
+    G_w = -+0.6 (complete wetting) the wall-row film's lead over the centre-line front grows
+    (Sec. 3, Figs. 5-8: a precursor film advancing ahead of the meniscus); at G_w = -+0.3 (partial
+    wetting) the lead is a constant set by the meniscus shape.  Lead p - z from the observables of
+    Sec. 3 (film front at a third of the bulk n_A on the wall rows, front on the centre line)."""
+    oracle.set_threads(8)
+    res = {}
+    for gw in ((-0.6, 0.6), (-0.3, 0.3)):
+        case = inputs.Case(inputs.Geometry(400, 22, 100, 380), inputs.Params(G=0.9, gw=gw), seed=3,
+                           liquid_x1=100)
+        o = oracle.Oracle.from_case(case).init(*case.fields())
+        rows = []
+        for t in range(500, 6001, 500):
+            o.step(500)
+            ob = o.observe()
+            assert not ob["flags"] & 2
+            rows.append((t, ob["z"], ob["precursor"]))
+        r = np.array(rows)
+        res[gw] = (r[:, 0], r[:, 2] - r[:, 1], r[:, 1])
+    t, lead, z = res[(-0.6, 0.6)]
+    m = t >= 1000
+    beta = np.polyfit(np.log(t[m]), np.log(lead[m]), 1)[0]
+    assert np.all(lead[m] > 0) and z[-1] > 20
+    assert lead[-1] - lead[1] >= 1.5
+    assert 0.03 < beta < 1.0
+    t, lead, z = res[(-0.3, 0.3)]
+    assert np.all(lead[m] > 0)
+    assert abs(lead[-1] - lead[1]) <= 0.3
