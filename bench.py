@@ -60,6 +60,8 @@ METRIC = "D2Q9 binary-SC MLUPS & % HBM peak; batched sweep vs surrogate at fixed
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_LUP = {"fused": 144, "two_kernel": 232}
 KERNEL_SRC = os.path.join(ROOT, "paper_0807_0602_amd", "csrc", "scf_kernels.hip")
+# the tile planner (strip widths, band heights) lives in the runtime: counters go stale with it too
+RUNTIME_SRC = os.path.join(ROOT, "paper_0807_0602_amd", "csrc", "scf_runtime.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_step_fused_capillary_16384x1024_traffic.json")
 KERNEL3_SRC = os.path.join(ROOT, "paper_0807_0602_amd", "csrc", "scf3d_kernels.hip")
 TRAFFIC3_FILE = os.path.join(ROOT, "profiles", "k3_fused_duct3d_512x182x182_traffic.json")
@@ -67,8 +69,13 @@ DUCT3D = (512, 182, 182, 128, 384)   # nx, ny, nz, x0, x1 of the 3-D duct worklo
 
 
 def kernel_hash(src: Optional[str] = None) -> str:
-    with open(src or KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    """First 16 hex digits of the sha256 of the kernel source (the 2-D kernels together with the
+    runtime that plans their tiles, by default)."""
+    h = hashlib.sha256()
+    for p in ([src] if src else [KERNEL_SRC, RUNTIME_SRC]):
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def measured_traffic(cells: int, schedule: dict, path: Optional[str] = None, src: Optional[str] = None,

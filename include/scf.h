@@ -93,16 +93,26 @@ typedef struct {
     int32_t order;        /* tile order: SCF_ORDER_STRIPS (all row chunks of a strip, then the next
                              strip) or SCF_ORDER_BANDS (all strips of a row band, then the next
                              band), optionally | SCF_ORDER_XCD (each of the 8 XCDs takes a
-                             contiguous eighth of that order instead of every 8th tile) */
+                             contiguous eighth of that order instead of every 8th tile).
+                             SCF_ORDER_PERSIST (| SCF_ORDER_XCD) instead launches one block per
+                             resident slot (CUs x the kernel's occupancy) and gives each block one
+                             equal, contiguous range of the sequence of (channel, strip, row),
+                             split into tiles at strip ends (cy is then not used; ranges are at
+                             least 16 rows); with SCF_ORDER_XCD each XCD takes a contiguous
+                             eighth of the ranges */
     int32_t graph_steps;  /* steps per captured HIP graph, 0 = launch every step directly */
     int32_t fuse;         /* time steps per pass of the fused step: 1, or 2 (temporal blocking:
                              each launch advances two steps, its tiles are bx - 6 columns wide,
-                             480 for bx = 512, and the intermediate populations stay on chip; an
+                             480 for bx = 512 and 224 for bx = 256 (edges on 128-byte lines), and
+                             the intermediate populations stay on chip; an
                              odd remainder of a step count is done by one single step).  Same
                              results bit for bit. */
+    int32_t blocks_per_cu; /* persistent schedules: blocks launched per compute unit, 0 = as many
+                             as the kernel's occupancy allows; scf_get_tile reports the number
+                             the two-step (fuse = 2) or single-step list uses.  Ignored otherwise. */
 } scf_tile;
 
-enum { SCF_ORDER_STRIPS = 0, SCF_ORDER_BANDS = 1, SCF_ORDER_XCD = 2 };
+enum { SCF_ORDER_STRIPS = 0, SCF_ORDER_BANDS = 1, SCF_ORDER_XCD = 2, SCF_ORDER_PERSIST = 4 };
 
 typedef struct scf_ctx scf_ctx;
 typedef struct scf_batch scf_batch;
@@ -152,7 +162,7 @@ int scf_set_variant(scf_ctx* ctx, int32_t variant);
 /* Set the launch schedule of the fused step: tiles of bx columns by cy rows (every other tile
  * of a strip walks its rows downward), taken by the blocks of one launch in the given order,
  * and one or two time steps per launch (fuse).  A new context starts with bx = 256, cy = 16,
- * order = SCF_ORDER_BANDS | SCF_ORDER_XCD, graph_steps = 64, fuse = 2.  Schedules change only the order of work, never
+ * order = SCF_ORDER_PERSIST | SCF_ORDER_XCD, graph_steps = 64, fuse = 2, blocks_per_cu = 0.  Schedules change only the order of work, never
  * the result.  Invalidates captured graphs.  Errors: SCF_EINVAL (bx not 64/128/256/512,
  * cy < 1, unknown order, graph_steps < 0, fuse not 1 or 2). */
 int scf_set_tile(scf_ctx* ctx, const scf_tile* tile);
@@ -163,6 +173,16 @@ int scf_get_tile(const scf_ctx* ctx, scf_tile* tile);
  * trial launch reads the resident buffer and writes the idle one, so the state is unchanged.
  * The graph length is kept.  Writes the chosen schedule to *chosen if non-NULL. */
 int scf_autotune(scf_ctx* ctx, int32_t trial_steps, scf_tile* chosen);
+
+/* scf_autotune with a cache: cache_path names a text file of lines
+ * "key bx cy order fuse blocks_per_cu ms_per_step", key a 64-bit hash (hex) of the device
+ * (architecture name, compute units), the library's schedule version and the channels'
+ * geometry class (nx, ny, x0, x1 and solid mask of every channel).  A line with this context's
+ * key applies its schedule without timing; otherwise the schedules are timed as scf_autotune
+ * does and one line is appended (the file is created if missing).  NULL cache_path: plain
+ * scf_autotune.  Errors as scf_autotune, and SCF_EINVAL when the line cannot be written (the
+ * tuned schedule is applied all the same). */
+int scf_autotune_cached(scf_ctx* ctx, int32_t trial_steps, const char* cache_path, scf_tile* chosen);
 
 /* Elapsed time step count of the context. */
 int64_t scf_time(const scf_ctx* ctx);
@@ -212,8 +232,10 @@ int scf_batch_get_density(scf_batch* b, int32_t c, double* nA, double* nB);
 int scf_batch_set_tile(scf_batch* b, const scf_tile* tile);
 int scf_batch_get_tile(const scf_batch* b, scf_tile* tile);
 
-/* Autotune the batched step as scf_autotune. */
+/* Autotune the batched step as scf_autotune, and with a cache as scf_autotune_cached (the key
+ * covers every channel of the batch, in order). */
 int scf_batch_autotune(scf_batch* b, int32_t trial_steps, scf_tile* chosen);
+int scf_batch_autotune_cached(scf_batch* b, int32_t trial_steps, const char* cache_path, scf_tile* chosen);
 
 void scf_batch_destroy(scf_batch* b);
 

@@ -42,14 +42,14 @@ class scf_obs(C.Structure):
 
 class scf_tile(C.Structure):
     _fields_ = [("bx", C.c_int32), ("cy", C.c_int32), ("order", C.c_int32), ("graph_steps", C.c_int32),
-                ("fuse", C.c_int32)]
+                ("fuse", C.c_int32), ("blocks_per_cu", C.c_int32)]
 
     def as_dict(self) -> dict:
         return {"bx": self.bx, "cy": self.cy, "order": self.order, "graph_steps": self.graph_steps,
-                "fuse": self.fuse}
+                "fuse": self.fuse, "blocks_per_cu": self.blocks_per_cu}
 
 
-SCF_ORDER_STRIPS, SCF_ORDER_BANDS, SCF_ORDER_XCD = 0, 1, 2
+SCF_ORDER_STRIPS, SCF_ORDER_BANDS, SCF_ORDER_XCD, SCF_ORDER_PERSIST = 0, 1, 2, 4
 
 
 class scf_sur_cfg(C.Structure):
@@ -97,6 +97,7 @@ _sig = {
     "scf_set_tile": (C.c_int, [_vp, C.POINTER(scf_tile)]),
     "scf_get_tile": (C.c_int, [_vp, C.POINTER(scf_tile)]),
     "scf_autotune": (C.c_int, [_vp, C.c_int32, C.POINTER(scf_tile)]),
+    "scf_autotune_cached": (C.c_int, [_vp, C.c_int32, C.c_char_p, C.POINTER(scf_tile)]),
     "scf_time": (C.c_int64, [_vp]),
     "scf_save": (C.c_int, [_vp, C.c_char_p]),
     "scf_load": (C.c_int, [_vp, C.c_char_p]),
@@ -112,6 +113,7 @@ _sig = {
     "scf_batch_set_tile": (C.c_int, [_vp, C.POINTER(scf_tile)]),
     "scf_batch_get_tile": (C.c_int, [_vp, C.POINTER(scf_tile)]),
     "scf_batch_autotune": (C.c_int, [_vp, C.c_int32, C.POINTER(scf_tile)]),
+    "scf_batch_autotune_cached": (C.c_int, [_vp, C.c_int32, C.c_char_p, C.POINTER(scf_tile)]),
     "scf_batch_destroy": (None, [_vp]),
     "scf_sur_workspace_bytes": (C.c_size_t, [C.POINTER(scf_sur_cfg)]),
     "scf_sur_create": (C.c_int, [C.POINTER(_vp), C.POINTER(scf_sur_cfg), _vp, C.c_size_t, _vp]),

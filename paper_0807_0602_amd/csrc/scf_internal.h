@@ -61,11 +61,17 @@ struct TileDesc {
 // Kernel launchers (all asynchronous on `stream`; return hipSuccess or the launch error).
 // launch_init builds the masked channels' codes, then the initial populations.
 hipError_t launch_init(const Chan* chans, const RowRef* rows, int nrows, float* ws, hipStream_t s);
+// Fused steps: with `first` non-NULL (persistent schedules) the launch has exactly `grid` blocks
+// and block b runs tiles [first[b], first[b+1]); otherwise blocks stride over the whole list.
 hipError_t launch_step_fused(int bx, bool masked, const Chan* chans, const TileDesc* tiles,
-                             int ntiles, int grid, float* ws, int src, hipStream_t s);
+                             int ntiles, const int32_t* first, int grid, float* ws, int src,
+                             hipStream_t s);
 // Two time steps in one pass; each tile carries its output width w <= bx - 6 (see k_step_fused2).
 hipError_t launch_step_fused2(int bx, bool masked, const Chan* chans, const TileDesc* tiles,
-                              int ntiles, int grid, float* ws, int src, hipStream_t s);
+                              int ntiles, const int32_t* first, int grid, float* ws, int src,
+                              hipStream_t s);
+// Blocks of the fused step (fuse 1 or 2) that one CU holds at once; 0 if the query fails.
+int resident_blocks_per_cu(int bx, bool masked, int fuse);
 hipError_t launch_step_two_kernel(const Chan* chans, const RowRef* rows, int nrows, float* ws,
                                   int src, hipStream_t s);
 hipError_t launch_observe(const Chan* chans, const RowRef* rows, int nrows, int nchan, float* ws,

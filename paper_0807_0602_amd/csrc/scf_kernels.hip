@@ -283,12 +283,16 @@ __device__ __forceinline__ void collide_store(const Chan& c, const float f[18], 
 template <int BX, bool MASK>
 __global__ void __launch_bounds__(BX)
 k_step_fused(const Chan* __restrict__ chans, const TileDesc* __restrict__ tiles, int ntiles,
-             float* __restrict__ ws, int src) {
+             const int32_t* __restrict__ first, float* __restrict__ ws, int src) {
     __shared__ float sn[2][4][BX + 2];
     const int tid = threadIdx.x;
     // Tiles are taken in list order; the host orders the list for the XCD placement it wants
-    // (blocks are dealt round-robin to the 8 XCDs).  Empty tiles pad such orders.
-    for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    // (blocks are dealt round-robin to the 8 XCDs).  Empty tiles pad such orders.  With a
+    // persistent schedule block b takes the tiles [first[b], first[b+1]) instead.
+    const int t_beg = first ? first[blockIdx.x] : (int)blockIdx.x;
+    const int t_end = first ? first[blockIdx.x + 1] : ntiles;
+    const int t_inc = first ? 1 : (int)gridDim.x;
+    for (int t = t_beg; t < t_end; t += t_inc) {
         const TileDesc td = tiles[t];
         if (td.ye <= td.yb) continue;
         const Chan c = chans[td.chan];
@@ -426,7 +430,7 @@ __device__ __forceinline__ void ring_sums(const float* Am, const float* Ao, cons
 template <int BX, bool MASK>
 __global__ void __launch_bounds__(BX) __attribute__((amdgpu_waves_per_eu(3, 3)))
 k_step_fused2(const Chan* __restrict__ chans, const TileDesc* __restrict__ tiles, int ntiles,
-              float* __restrict__ ws, int src) {
+              const int32_t* __restrict__ first, float* __restrict__ ws, int src) {
     constexpr int NW = BX / 64;
     __shared__ float r1[2][3][BX];       // n(t)
     __shared__ float r2[2][3][BX];       // n(t + 1)
@@ -438,7 +442,11 @@ k_step_fused2(const Chan* __restrict__ chans, const TileDesc* __restrict__ tiles
     const int tid = threadIdx.x;
     const int lane = tid & 63, wv = tid >> 6;
     const int opp[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
-    for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    // grid-stride over the list, or block b's own range [first[b], first[b+1]) (persistent)
+    const int t_beg = first ? first[blockIdx.x] : (int)blockIdx.x;
+    const int t_end = first ? first[blockIdx.x + 1] : ntiles;
+    const int t_inc = first ? 1 : (int)gridDim.x;
+    for (int t = t_beg; t < t_end; t += t_inc) {
         const TileDesc td = tiles[t];
         if (td.ye <= td.yb) continue;
         const Chan c = chans[td.chan];
@@ -897,26 +905,48 @@ __global__ void k_bump(int32_t* counter) {
     if (threadIdx.x == 0 && blockIdx.x == 0) *counter = *counter + 1;
 }
 
+// grid: blocks of the launch; with `first` (persistent schedules) exactly `grid` blocks, each
+// with its own tile range, otherwise min(grid, ntiles) blocks (all tiles when grid <= 0).
+inline int grid_of(int grid, int ntiles, const int32_t* first) {
+    if (first) return grid;
+    return grid > 0 ? min(grid, ntiles) : ntiles;
+}
+
 template <int BX>
 hipError_t launch_fused_bx(bool masked, const Chan* chans, const TileDesc* tiles, int ntiles,
-                           int grid, float* ws, int src, hipStream_t s) {
-    const int g = grid > 0 ? min(grid, ntiles) : ntiles;
+                           const int32_t* first, int grid, float* ws, int src, hipStream_t s) {
+    const int g = grid_of(grid, ntiles, first);
+    if (g <= 0) return hipSuccess;
     if (masked)
-        hipLaunchKernelGGL((k_step_fused<BX, true>), dim3(g), dim3(BX), 0, s, chans, tiles, ntiles, ws, src);
+        hipLaunchKernelGGL((k_step_fused<BX, true>), dim3(g), dim3(BX), 0, s, chans, tiles, ntiles, first, ws, src);
     else
-        hipLaunchKernelGGL((k_step_fused<BX, false>), dim3(g), dim3(BX), 0, s, chans, tiles, ntiles, ws, src);
+        hipLaunchKernelGGL((k_step_fused<BX, false>), dim3(g), dim3(BX), 0, s, chans, tiles, ntiles, first, ws, src);
     return hipGetLastError();
 }
 
 template <int BX>
 hipError_t launch_fused2_bx(bool masked, const Chan* chans, const TileDesc* tiles, int ntiles,
-                            int grid, float* ws, int src, hipStream_t s) {
-    const int g = grid > 0 ? min(grid, ntiles) : ntiles;
+                            const int32_t* first, int grid, float* ws, int src, hipStream_t s) {
+    const int g = grid_of(grid, ntiles, first);
+    if (g <= 0) return hipSuccess;
     if (masked)
-        hipLaunchKernelGGL((k_step_fused2<BX, true>), dim3(g), dim3(BX), 0, s, chans, tiles, ntiles, ws, src);
+        hipLaunchKernelGGL((k_step_fused2<BX, true>), dim3(g), dim3(BX), 0, s, chans, tiles, ntiles, first, ws, src);
     else
-        hipLaunchKernelGGL((k_step_fused2<BX, false>), dim3(g), dim3(BX), 0, s, chans, tiles, ntiles, ws, src);
+        hipLaunchKernelGGL((k_step_fused2<BX, false>), dim3(g), dim3(BX), 0, s, chans, tiles, ntiles, first, ws, src);
     return hipGetLastError();
+}
+
+template <int BX>
+int resident_bx(bool masked, int fuse) {
+    int n = 0;
+    hipError_t e;
+    if (fuse == 2)
+        e = masked ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step_fused2<BX, true>, BX, 0)
+                   : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step_fused2<BX, false>, BX, 0);
+    else
+        e = masked ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step_fused<BX, true>, BX, 0)
+                   : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step_fused<BX, false>, BX, 0);
+    return e == hipSuccess ? n : 0;
 }
 
 // Solid-neighbourhood codes of masked channels from the staged uint8 mask (ny*nx bytes after
@@ -954,24 +984,36 @@ hipError_t launch_init(const Chan* chans, const RowRef* rows, int nrows, float* 
 }
 
 hipError_t launch_step_fused(int bx, bool masked, const Chan* chans, const TileDesc* tiles,
-                             int ntiles, int grid, float* ws, int src, hipStream_t s) {
+                             int ntiles, const int32_t* first, int grid, float* ws, int src,
+                             hipStream_t s) {
     switch (bx) {
-        case 64: return launch_fused_bx<64>(masked, chans, tiles, ntiles, grid, ws, src, s);
-        case 128: return launch_fused_bx<128>(masked, chans, tiles, ntiles, grid, ws, src, s);
-        case 256: return launch_fused_bx<256>(masked, chans, tiles, ntiles, grid, ws, src, s);
-        case 512: return launch_fused_bx<512>(masked, chans, tiles, ntiles, grid, ws, src, s);
+        case 64: return launch_fused_bx<64>(masked, chans, tiles, ntiles, first, grid, ws, src, s);
+        case 128: return launch_fused_bx<128>(masked, chans, tiles, ntiles, first, grid, ws, src, s);
+        case 256: return launch_fused_bx<256>(masked, chans, tiles, ntiles, first, grid, ws, src, s);
+        case 512: return launch_fused_bx<512>(masked, chans, tiles, ntiles, first, grid, ws, src, s);
         default: return hipErrorInvalidValue;
     }
 }
 
 hipError_t launch_step_fused2(int bx, bool masked, const Chan* chans, const TileDesc* tiles,
-                              int ntiles, int grid, float* ws, int src, hipStream_t s) {
+                              int ntiles, const int32_t* first, int grid, float* ws, int src,
+                              hipStream_t s) {
     switch (bx) {
-        case 64: return launch_fused2_bx<64>(masked, chans, tiles, ntiles, grid, ws, src, s);
-        case 128: return launch_fused2_bx<128>(masked, chans, tiles, ntiles, grid, ws, src, s);
-        case 256: return launch_fused2_bx<256>(masked, chans, tiles, ntiles, grid, ws, src, s);
-        case 512: return launch_fused2_bx<512>(masked, chans, tiles, ntiles, grid, ws, src, s);
+        case 64: return launch_fused2_bx<64>(masked, chans, tiles, ntiles, first, grid, ws, src, s);
+        case 128: return launch_fused2_bx<128>(masked, chans, tiles, ntiles, first, grid, ws, src, s);
+        case 256: return launch_fused2_bx<256>(masked, chans, tiles, ntiles, first, grid, ws, src, s);
+        case 512: return launch_fused2_bx<512>(masked, chans, tiles, ntiles, first, grid, ws, src, s);
         default: return hipErrorInvalidValue;
+    }
+}
+
+int resident_blocks_per_cu(int bx, bool masked, int fuse) {
+    switch (bx) {
+        case 64: return resident_bx<64>(masked, fuse);
+        case 128: return resident_bx<128>(masked, fuse);
+        case 256: return resident_bx<256>(masked, fuse);
+        case 512: return resident_bx<512>(masked, fuse);
+        default: return 0;
     }
 }
 

@@ -38,6 +38,13 @@ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 int pitch_of(int nx) { return (nx + 63) / 64 * 64; }
 
 constexpr int kMaxRowsPerGeom = 1 << 20;
+// Persistent schedules: at most this many blocks per launch, and ranges of at least kMinRange
+// rows (each range pays the pipeline's start-up rows once).
+constexpr int kMaxPersistBlocks = 8192;
+constexpr int kMinRange = 16;
+// Version of the schedule space and kernels in the autotuner cache key (a cached schedule from
+// another version is timed again).
+constexpr int kTuneVersion = 4;
 constexpr int kPlanesPerChannel = 38;   // 2 x 18 population planes + 2 density planes
 
 // Float planes of one channel: populations and densities, plus one for the uint16 codes of a
@@ -88,7 +95,7 @@ bool params_ok(const scf_params* p, std::string* why) {
 }
 
 struct Layout {
-    size_t chans = 0, rows = 0, tiles = 0, parts = 0, now = 0, ring = 0, counter = 0;
+    size_t chans = 0, rows = 0, tiles = 0, first = 0, parts = 0, now = 0, ring = 0, counter = 0;
     std::vector<size_t> chan_off;   // byte offset of each channel's region
     size_t total = 0;
     int nrows = 0, max_tiles = 0;
@@ -103,9 +110,12 @@ Layout plan(int nchan, const scf_geometry* g, int max_samples) {
     L.chans = off; off = align_up(off + sizeof(scf::Chan) * nchan, 256);
     for (int c = 0; c < nchan; ++c) { L.nrows += g[c].ny; L.max_tiles += max_tiles_of(g[c]); }
     L.rows = off; off = align_up(off + sizeof(scf::RowRef) * L.nrows, 256);
-    L.max_tiles += 8;   // padding of the XCD-contiguous order
-    // two lists: single-step tiles, then the two-step tiles
+    // padding of the XCD-contiguous order; a persistent schedule splits at most one range per
+    // block at strip ends beyond the strips themselves
+    L.max_tiles += 8 + kMaxPersistBlocks;
+    // two lists: single-step tiles, then the two-step tiles; then each list's per-block offsets
     L.tiles = off; off = align_up(off + sizeof(scf::TileDesc) * 2 * (size_t)L.max_tiles, 256);
+    L.first = off; off = align_up(off + sizeof(int32_t) * 2 * (size_t)(kMaxPersistBlocks + 1), 256);
     L.parts = off; off = align_up(off + sizeof(scf::RowPartial) * L.nrows, 256);
     L.now = off; off = align_up(off + sizeof(scf::ObsRec) * nchan, 256);
     L.ring = off; off = align_up(off + sizeof(scf::ObsRec) * (size_t)nchan * max_samples, 256);
@@ -162,9 +172,17 @@ struct Engine {
     int cur = 0;
     int64_t t = 0;
     int variant = SCF_VARIANT_FUSED;
-    // default schedule: the one the autotuner picks for the 16384 x 1024 capillary
-    int bx = 256, cy = 16, order = SCF_ORDER_BANDS | SCF_ORDER_XCD, graph_steps = 64, grid = 0, fuse = 2;
+    // default schedule: the one the autotuner picks for the 16384 x 1024 capillary (two steps
+    // per launch, 256-wide blocks on 224-column strips, persistent strip-aligned bands dealt to
+    // the XCDs in eighths)
+    int bx = 256, cy = 16, order = SCF_ORDER_PERSIST | SCF_ORDER_XCD, graph_steps = 64, fuse = 2;
     int ntiles = 0, ntiles2 = 0;
+    // blocks of the single-step and two-step launches under a persistent schedule (0: one
+    // block per tile), and the device's compute units
+    int grid1 = 0, grid2 = 0;
+    int cus = 0;
+    int bpc = 0;   // requested blocks per CU of persistent schedules (0: occupancy)
+    float tuned_ms = 0.0f;   // time per step of the last autotuned schedule
     hipGraphExec_t g_steps[2] = {nullptr, nullptr};
     hipGraphExec_t g_sample[2] = {nullptr, nullptr};
     int sample_every = 0, max_samples = 1;
@@ -178,6 +196,9 @@ struct Engine {
     scf::RowRef* d_rows() const { return reinterpret_cast<scf::RowRef*>(ws + lay.rows); }
     scf::TileDesc* d_tiles() const { return reinterpret_cast<scf::TileDesc*>(ws + lay.tiles); }
     scf::TileDesc* d_tiles2() const { return d_tiles() + lay.max_tiles; }
+    int32_t* d_first() const { return reinterpret_cast<int32_t*>(ws + lay.first); }
+    int32_t* d_first2() const { return d_first() + kMaxPersistBlocks + 1; }
+    bool persistent() const { return (order & SCF_ORDER_PERSIST) != 0; }
     scf::RowPartial* d_parts() const { return reinterpret_cast<scf::RowPartial*>(ws + lay.parts); }
     scf::ObsRec* d_now() const { return reinterpret_cast<scf::ObsRec*>(ws + lay.now); }
     scf::ObsRec* d_ring() const { return reinterpret_cast<scf::ObsRec*>(ws + lay.ring); }
@@ -240,23 +261,121 @@ struct Engine {
         return out;
     }
 
-    // Output columns per block of the two-step kernel: bx - 6 (its lanes pull three extra
-    // columns each side), 480 for 512-wide blocks so that strip edges fall on 128-byte lines
-    // (measured faster there; narrower blocks lose too much).
-    static int strip2(int bxv) { return bxv == 512 ? 480 : bxv - 6; }
+    // Persistent schedule over strips `stripw` wide for `nblocks` blocks, at most one tile per
+    // block, so the whole step runs in one round with the tallest bands that fit: every channel's
+    // rows are cut into k_c near-equal bands with k_c = ceil(ny_c / R), R the smallest band
+    // height (>= kMinRange) for which the tiles, strips x bands summed over channels, number at
+    // most nblocks.  Bands are aligned across the strips of a channel and tiles are listed by
+    // (channel, band, strip), so horizontally adjacent tiles run at the same time and share the
+    // cache lines at their edges.  With SCF_ORDER_XCD (nblocks a multiple of 8) XCD x takes the
+    // x-th contiguous eighth of the list: block b, on XCD b mod 8, runs tile
+    // floor(T (b mod 8) / 8) + b / 8 of its eighth.  Odd bands walk downward in the single-step
+    // kernel, so two bands meet at their shared rows.  first[b] indexes block b's tile.
+    void make_tiles_persist(int stripw, int nblocks, int ord, std::vector<scf::TileDesc>& tl,
+                            std::vector<int32_t>& first) const {
+        std::vector<int> nstrip(nchan);
+        int maxny = 1;
+        for (int c = 0; c < nchan; ++c) {
+            nstrip[c] = (geom[c].nx + stripw - 1) / stripw;
+            maxny = std::max(maxny, geom[c].ny);
+        }
+        auto count = [&](int R) {
+            int64_t T = 0;
+            for (int c = 0; c < nchan; ++c) T += (int64_t)nstrip[c] * ((geom[c].ny + R - 1) / R);
+            return T;
+        };
+        int lo = std::min(kMinRange, maxny), hi = maxny;   // count(maxny) = number of strips
+        while (lo < hi) {
+            const int mid = (lo + hi) / 2;
+            if (count(mid) <= nblocks) hi = mid; else lo = mid + 1;
+        }
+        const int R = lo;
+        tl.clear();
+        for (int c = 0; c < nchan; ++c) {
+            const int ny = geom[c].ny, k = (ny + R - 1) / R;
+            for (int j = 0; j < k; ++j)
+                for (int s_ = 0; s_ < nstrip[c]; ++s_) {
+                    scf::TileDesc td;
+                    std::memset(&td, 0, sizeof td);
+                    td.chan = c;
+                    td.xb = s_ * stripw;
+                    td.yb = (int)((int64_t)j * ny / k);
+                    td.ye = (int)((int64_t)(j + 1) * ny / k);
+                    td.down = j & 1;
+                    td.w = stripw;
+                    tl.push_back(td);
+                }
+        }
+        // more strips than blocks (R = maxny still too many): blocks take several tiles each
+        const int64_t T = (int64_t)tl.size();
+        const bool xcd = (ord & SCF_ORDER_XCD) && nblocks % 8 == 0;
+        first.assign((size_t)nblocks + 1, 0);
+        std::vector<scf::TileDesc> out;
+        out.reserve(tl.size());
+        for (int b = 0; b < nblocks; ++b) {
+            first[b] = (int32_t)out.size();
+            // block b's share [t0, t1) of the list
+            int64_t t0, t1;
+            if (xcd) {
+                const int x = b % 8, i = b / 8, per = nblocks / 8;
+                const int64_t e0 = T * x / 8, e1 = T * (x + 1) / 8;   // XCD x's eighth
+                t0 = e0 + (e1 - e0) * i / per;
+                t1 = e0 + (e1 - e0) * (i + 1) / per;
+            } else {
+                t0 = T * b / nblocks;
+                t1 = T * (b + 1) / nblocks;
+            }
+            for (int64_t t = t0; t < t1; ++t) out.push_back(tl[(size_t)t]);
+        }
+        first[nblocks] = (int32_t)out.size();
+        tl.swap(out);
+    }
+
+    // Blocks of a persistent launch: every CU filled to the kernel's occupancy (a multiple of 8
+    // for the XCD order); 0 if the occupancy query fails.
+    int persist_blocks(int bxv, int fz, int ord) const {
+        const int occ = bpc > 0 ? bpc : scf::resident_blocks_per_cu(bxv, any_masked, fz);
+        if (occ < 1 || cus < 1) return 0;
+        int n = std::min(cus * occ, kMaxPersistBlocks);
+        if ((ord & SCF_ORDER_XCD) && n >= 8) n -= n % 8;
+        return n;
+    }
+
+    // Output columns per block of the two-step kernel: at most bx - 6 (its lanes pull three
+    // extra columns each side); 480 for 512-wide and 224 for 256-wide blocks, so that strip edges
+    // fall on 128-byte lines (measured faster although 26-32 lanes idle: a misaligned edge line
+    // is read and written by two strips at different times); bx - 6 for narrower blocks.
+    static int strip2(int bxv) { return bxv == 512 ? 480 : bxv == 256 ? 224 : bxv - 6; }
 
     int upload_tiles(int bxv, int cyv, int ord) {
-        std::vector<scf::TileDesc> tl = make_tiles(bxv, cyv, ord);
-        std::vector<scf::TileDesc> tl2 = make_tiles(strip2(bxv), cyv, ord);
+        std::vector<scf::TileDesc> tl, tl2;
+        std::vector<int32_t> f1, f2;
+        int g1 = 0, g2 = 0;
+        if (ord & SCF_ORDER_PERSIST) {
+            g1 = persist_blocks(bxv, 1, ord);
+            g2 = persist_blocks(bxv, 2, ord);
+            if (!g1 || !g2) return fail(SCF_EDEVICE, "occupancy query for the persistent schedule failed");
+            make_tiles_persist(bxv, g1, ord, tl, f1);
+            make_tiles_persist(strip2(bxv), g2, ord, tl2, f2);
+        } else {
+            tl = make_tiles(bxv, cyv, ord);
+            tl2 = make_tiles(strip2(bxv), cyv, ord);
+        }
         if ((int)tl.size() > lay.max_tiles || (int)tl2.size() > lay.max_tiles)
             return fail(SCF_EINVAL, "tile list exceeds its reserved space");
         HIP_TRY(hipMemcpyAsync(d_tiles(), tl.data(), sizeof(scf::TileDesc) * tl.size(),
                                hipMemcpyHostToDevice, stream));
         HIP_TRY(hipMemcpyAsync(d_tiles2(), tl2.data(), sizeof(scf::TileDesc) * tl2.size(),
                                hipMemcpyHostToDevice, stream));
+        if (ord & SCF_ORDER_PERSIST) {
+            HIP_TRY(hipMemcpyAsync(d_first(), f1.data(), sizeof(int32_t) * f1.size(), hipMemcpyHostToDevice, stream));
+            HIP_TRY(hipMemcpyAsync(d_first2(), f2.data(), sizeof(int32_t) * f2.size(), hipMemcpyHostToDevice, stream));
+        }
         HIP_TRY(hipStreamSynchronize(stream));
         ntiles = (int)tl.size();
         ntiles2 = (int)tl2.size();
+        grid1 = g1;
+        grid2 = g2;
         bx = bxv;
         cy = cyv;
         order = ord;
@@ -270,11 +389,14 @@ struct Engine {
 
     // One launch of `k` (1 or 2) steps reading buffer src and writing src ^ 1.
     hipError_t launch_steps(hipStream_t s, int src, int k) const {
+        const bool p = persistent();
         if (k == 2)
-            return scf::launch_step_fused2(bx, any_masked, d_chans(), d_tiles2(), ntiles2, grid, base(), src, s);
+            return scf::launch_step_fused2(bx, any_masked, d_chans(), d_tiles2(), ntiles2,
+                                           p ? d_first2() : nullptr, grid2, base(), src, s);
         if (variant == SCF_VARIANT_TWO_KERNEL)
             return scf::launch_step_two_kernel(d_chans(), d_rows(), lay.nrows, base(), src, s);
-        return scf::launch_step_fused(bx, any_masked, d_chans(), d_tiles(), ntiles, grid, base(), src, s);
+        return scf::launch_step_fused(bx, any_masked, d_chans(), d_tiles(), ntiles, p ? d_first() : nullptr,
+                                      grid1, base(), src, s);
     }
 
     // Launches that advance n steps (each flips the resident buffer once).
@@ -387,6 +509,11 @@ struct Engine {
             if (!rhoA || !rhoB || !rhoA[c] || !rhoB[c]) return fail(SCF_EINVAL, "density field is NULL");
         }
         if (max_samp < 1) return fail(SCF_EINVAL, "max_samples must be >= 1");
+        {
+            int dev = 0;
+            HIP_TRY(hipGetDevice(&dev));
+            HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+        }
         nchan = nch;
         geom.assign(g, g + nch);
         mhash.clear();
@@ -445,13 +572,16 @@ struct Engine {
         if (tl->bx != 64 && tl->bx != 128 && tl->bx != 256 && tl->bx != 512)
             return fail(SCF_EINVAL, "bx must be 64, 128, 256 or 512");
         if (tl->cy < 1) return fail(SCF_EINVAL, "cy must be >= 1");
-        if (tl->order < 0 || tl->order > (SCF_ORDER_BANDS | SCF_ORDER_XCD)) return fail(SCF_EINVAL, "unknown order");
+        if (tl->order < 0 || tl->order > (SCF_ORDER_BANDS | SCF_ORDER_XCD | SCF_ORDER_PERSIST))
+            return fail(SCF_EINVAL, "unknown order");
         if (tl->graph_steps < 0) return fail(SCF_EINVAL, "graph_steps must be >= 0");
         if (tl->fuse != 1 && tl->fuse != 2) return fail(SCF_EINVAL, "fuse must be 1 or 2");
+        if (tl->blocks_per_cu < 0 || tl->blocks_per_cu > 32) return fail(SCF_EINVAL, "blocks_per_cu must be in [0, 32]");
         HIP_TRY(hipStreamSynchronize(stream));
         drop_graphs();
         graph_steps = tl->graph_steps;
         fuse = tl->fuse;
+        bpc = tl->blocks_per_cu;
         return upload_tiles(tl->bx, tl->cy, tl->order);
     }
 
@@ -461,6 +591,8 @@ struct Engine {
         tl->order = order;
         tl->graph_steps = graph_steps;
         tl->fuse = fuse;
+        const int g = fuse == 2 ? grid2 : grid1;
+        tl->blocks_per_cu = (persistent() && cus > 0) ? g / cus : 0;
     }
 
     // Time each candidate by repeated steps that all read the resident buffer and write the
@@ -477,6 +609,7 @@ struct Engine {
         HIP_TRY(hipEventCreate(&e1));
         const int saved_variant = variant;
         variant = SCF_VARIANT_FUSED;
+        bpc = 0;   // persistent candidates fill the CUs to the kernel's occupancy
         struct Cand { int bx, cy, ord, fuse; float ms; };   // ms per time step
         std::vector<Cand> cands;
         for (int ord = 0; ord < 4; ++ord)
@@ -485,6 +618,10 @@ struct Engine {
                     if (cyv != (1 << 30) && cyv >= maxny) continue;
                     for (int k = 1; k <= 2; ++k) cands.push_back({bxv, cyv, ord, k, 0.0f});
                 }
+        // persistent schedules (range lengths follow from the occupancy, cy is not used)
+        for (int ord : {(int)SCF_ORDER_PERSIST, (int)(SCF_ORDER_PERSIST | SCF_ORDER_XCD)})
+            for (int bxv : bxs)
+                for (int k = 1; k <= 2; ++k) cands.push_back({bxv, cy, ord, k, 0.0f});
         // time every candidate with `trial` launches, then the best eight again with four
         // times as many, and keep the fastest of the second round
         auto time_cand = [&](Cand& cd, int launches) -> int {
@@ -516,9 +653,78 @@ struct Engine {
         if (rc) return rc;
         drop_graphs();
         fuse = cands[0].fuse;
+        tuned_ms = cands[0].ms;
         rc = upload_tiles(cands[0].bx, cands[0].cy, cands[0].ord);
         if (rc) return rc;
         if (chosen) get_tile(chosen);
+        return SCF_OK;
+    }
+
+    // Key of the autotuner cache: the device (architecture name and compute units) and the
+    // geometry class of the channels (sizes, wall extents, masks) in channel order, FNV-1a over
+    // their values.  Schedules change only the order of work, so nothing else enters.
+    uint64_t tune_key() const {
+        uint64_t h = 1469598103934665603ull;
+        auto mix = [&](uint64_t v) {
+            for (int i = 0; i < 8; ++i) {
+                h ^= (v >> (8 * i)) & 0xffu;
+                h *= 1099511628211ull;
+            }
+        };
+        int dev = 0;
+        hipDeviceProp_t prop;
+        if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+            for (const char* p = prop.gcnArchName; *p; ++p) mix((uint64_t)(unsigned char)*p);
+        mix((uint64_t)kTuneVersion);
+        mix((uint64_t)cus);
+        mix((uint64_t)nchan);
+        for (int c = 0; c < nchan; ++c) {
+            mix((uint64_t)geom[c].nx);
+            mix((uint64_t)geom[c].ny);
+            mix((uint64_t)geom[c].x0);
+            mix((uint64_t)geom[c].x1);
+            mix(mhash[c]);
+        }
+        return h;
+    }
+
+    // autotune() with a cache file of lines "key bx cy order fuse blocks_per_cu ms_per_step":
+    // a line with this context's key applies that schedule without timing; otherwise the
+    // schedules are timed and the choice is appended.  The graph length is kept either way.
+    int autotune_cached(int trial, const char* path, scf_tile* chosen) {
+        if (!path) return autotune(trial, chosen);
+        const uint64_t key = tune_key();
+        if (FILE* f = std::fopen(path, "r")) {
+            char line[256];
+            bool found = false;
+            scf_tile tl;
+            while (std::fgets(line, sizeof line, f)) {
+                unsigned long long k = 0;
+                int v[5];
+                float ms = 0.0f;
+                if (std::sscanf(line, "%llx %d %d %d %d %d %f", &k, &v[0], &v[1], &v[2], &v[3], &v[4], &ms) == 7 &&
+                    k == key) {
+                    tl.bx = v[0]; tl.cy = v[1]; tl.order = v[2]; tl.fuse = v[3]; tl.blocks_per_cu = v[4];
+                    found = true;   // the last matching line wins
+                }
+            }
+            std::fclose(f);
+            if (found) {
+                tl.graph_steps = graph_steps;
+                int rc = set_tile(&tl);
+                if (rc) return rc;
+                if (chosen) get_tile(chosen);
+                return SCF_OK;
+            }
+        }
+        int rc = autotune(trial, chosen);
+        if (rc) return rc;
+        FILE* f = std::fopen(path, "a");
+        if (!f) return fail(SCF_EINVAL, std::string("autotuner cache not writable (schedule applied): ") + path);
+        const bool ok = std::fprintf(f, "%016llx %d %d %d %d %d %.6f\n", (unsigned long long)key, bx, cy, order, fuse,
+                                     bpc, tuned_ms) > 0;
+        if (std::fclose(f) != 0 || !ok)
+            return fail(SCF_EINVAL, std::string("autotuner cache write failed (schedule applied): ") + path);
         return SCF_OK;
     }
 
@@ -643,6 +849,11 @@ int scf_get_tile(const scf_ctx* ctx, scf_tile* tile) {
 int scf_autotune(scf_ctx* ctx, int32_t trial_steps, scf_tile* chosen) {
     if (!ctx) return fail(SCF_EINVAL, "NULL context");
     return ctx->e.autotune(trial_steps, chosen);
+}
+
+int scf_autotune_cached(scf_ctx* ctx, int32_t trial_steps, const char* cache_path, scf_tile* chosen) {
+    if (!ctx) return fail(SCF_EINVAL, "NULL context");
+    return ctx->e.autotune_cached(trial_steps, cache_path, chosen);
 }
 
 int64_t scf_time(const scf_ctx* ctx) { return ctx ? ctx->e.t : -1; }
@@ -799,6 +1010,11 @@ int scf_batch_get_tile(const scf_batch* b, scf_tile* tile) {
 int scf_batch_autotune(scf_batch* b, int32_t trial_steps, scf_tile* chosen) {
     if (!b) return fail(SCF_EINVAL, "NULL batch");
     return b->e.autotune(trial_steps, chosen);
+}
+
+int scf_batch_autotune_cached(scf_batch* b, int32_t trial_steps, const char* cache_path, scf_tile* chosen) {
+    if (!b) return fail(SCF_EINVAL, "NULL batch");
+    return b->e.autotune_cached(trial_steps, cache_path, chosen);
 }
 
 void scf_batch_destroy(scf_batch* b) {

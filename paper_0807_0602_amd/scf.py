@@ -119,8 +119,9 @@ class Channel:
     def set_variant(self, variant: int) -> None:
         L.check(L.scf_set_variant(self._h, int(variant)))
 
-    def set_tile(self, bx: int, cy: int, graph_steps: int = 64, order: int = 0, fuse: int = 1) -> None:
-        t = L.scf_tile(int(bx), int(cy), int(order), int(graph_steps), int(fuse))
+    def set_tile(self, bx: int, cy: int, graph_steps: int = 64, order: int = 0, fuse: int = 1,
+                 blocks_per_cu: int = 0) -> None:
+        t = L.scf_tile(int(bx), int(cy), int(order), int(graph_steps), int(fuse), int(blocks_per_cu))
         L.check(L.scf_set_tile(self._h, C.byref(t)))
 
     def tile(self) -> dict:
@@ -128,9 +129,14 @@ class Channel:
         L.check(L.scf_get_tile(self._h, C.byref(t)))
         return t.as_dict()
 
-    def autotune(self, trial_steps: int = 20) -> dict:
+    def autotune(self, trial_steps: int = 20, cache: Optional[str] = None) -> dict:
+        """Time the candidate schedules and keep the fastest; with `cache` (a file path) reuse or
+        record the choice for this geometry class and device (scf_autotune_cached)."""
         t = L.scf_tile()
-        L.check(L.scf_autotune(self._h, int(trial_steps), C.byref(t)))
+        if cache is None:
+            L.check(L.scf_autotune(self._h, int(trial_steps), C.byref(t)))
+        else:
+            L.check(L.scf_autotune_cached(self._h, int(trial_steps), str(cache).encode(), C.byref(t)))
         return t.as_dict()
 
     def save(self, path: str) -> None:
@@ -203,8 +209,9 @@ class Batch:
         L.check(L.scf_batch_get_density(self._h, int(c), _dptr(a), _dptr(b)))
         return a, b
 
-    def set_tile(self, bx: int, cy: int, graph_steps: int = 64, order: int = 0, fuse: int = 1) -> None:
-        t = L.scf_tile(int(bx), int(cy), int(order), int(graph_steps), int(fuse))
+    def set_tile(self, bx: int, cy: int, graph_steps: int = 64, order: int = 0, fuse: int = 1,
+                 blocks_per_cu: int = 0) -> None:
+        t = L.scf_tile(int(bx), int(cy), int(order), int(graph_steps), int(fuse), int(blocks_per_cu))
         L.check(L.scf_batch_set_tile(self._h, C.byref(t)))
 
     def tile(self) -> dict:
@@ -212,9 +219,13 @@ class Batch:
         L.check(L.scf_batch_get_tile(self._h, C.byref(t)))
         return t.as_dict()
 
-    def autotune(self, trial_steps: int = 10) -> dict:
+    def autotune(self, trial_steps: int = 10, cache: Optional[str] = None) -> dict:
+        """As Channel.autotune, for the whole batch."""
         t = L.scf_tile()
-        L.check(L.scf_batch_autotune(self._h, int(trial_steps), C.byref(t)))
+        if cache is None:
+            L.check(L.scf_batch_autotune(self._h, int(trial_steps), C.byref(t)))
+        else:
+            L.check(L.scf_batch_autotune_cached(self._h, int(trial_steps), str(cache).encode(), C.byref(t)))
         return t.as_dict()
 
 

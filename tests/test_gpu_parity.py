@@ -284,8 +284,9 @@ def test_batch_against_oracle(scf):
 
 
 # ------------------------------------------------------------------------------ full sizes
-# the schedule bench.py's autotuner picks for the 16384 x 1024 capillary (two steps per launch)
-BENCH_TILE = dict(bx=256, cy=16, graph_steps=64, order=3, fuse=2)
+# the schedule bench.py's autotuner picks for the 16384 x 1024 capillary (two steps per launch,
+# 256-wide blocks on 224-column strips, persistent strip-aligned bands in XCD eighths)
+BENCH_TILE = dict(bx=256, cy=16, graph_steps=64, order=6, fuse=2)
 
 
 def _window_check(scf, case, T, centres, half, tile=BENCH_TILE):
