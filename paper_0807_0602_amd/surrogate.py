@@ -147,10 +147,14 @@ class Network:
 RATIOS = (1, 2, 5, 10)
 
 
-def draw_cases(n: int, seed: int, steps: int = 50_000, every: int = 100) -> List[Case]:
+def draw_cases(n: int, seed: int, steps: int = 50_000, every: int = 100, grid: bool = False) -> List[Case]:
     """n channels with G_wA ~ U[-0.3, 0.3], H ~ U{20..160}, L ~ U{512..4096} in multiples of 4
-    and r uniform over {1, 2, 5, 10} (tau pair per the working map of inputs.TAU_FOR_RATIO)."""
-    from .inputs import sweep_channel
+    and r uniform over {1, 2, 5, 10} (tau pair per the working map of inputs.TAU_FOR_RATIO).
+    grid: H and L uniform over the calibration sweep's own sets instead, {20, 40, 80, 160} and
+    {512, 1024, 2048, 4096} (the sweep recipe inputs.sweep_draws with this seed)."""
+    from .inputs import sweep_channel, sweep_draws
+    if grid:
+        return sweep_draws(n, seed=seed, steps=steps, sample_every=every)
     rng = np.random.default_rng(seed)
     out = []
     for c in range(n):
@@ -187,12 +191,15 @@ def simulate(cases: Sequence[Case], steps: int, every: int, group: int = 64, log
 
 def dataset(cases: Sequence[Case], traj: np.ndarray, with_length: bool = False, t_min: float = 100.0):
     """(X, T, w, keep): features, targets (z/H, p/H), weights H^2, and the mask of kept samples
-    (t >= t_min, finite z and p, no instability so far)."""
+    (t >= t_min, finite z and p, no instability so far, and the liquid reservoir not yet drained
+    to its centre: from that flag on the film level is read in gas and the front is no longer
+    fed by a reservoir, so the samples no longer describe capillary filling)."""
     Xs, Ts, ws, keep = [], [], [], []
     for case, tr in zip(cases, traj):
         H = float(case.geom.ny - 2)
-        t, z, p, unst = tr[:, 0], tr[:, 1], tr[:, 2], tr[:, 4]
-        ok = (t >= t_min) & np.isfinite(z) & np.isfinite(p) & (unst == 0)
+        t, z, p, flags, unst = tr[:, 0], tr[:, 1], tr[:, 2], tr[:, 3], tr[:, 4]
+        drained = np.cumsum((np.nan_to_num(flags).astype(np.int64) & 1) > 0) > 0
+        ok = (t >= t_min) & np.isfinite(z) & np.isfinite(p) & (unst == 0) & ~drained
         Xs.append(features(case, np.maximum(t, 1.0), with_length))
         Ts.append(np.stack([z / H, p / H], axis=1))
         ws.append(np.full(t.shape, H * H))
@@ -281,6 +288,7 @@ def _main(argv=None) -> int:
     g.add_argument("--n", type=int, required=True); g.add_argument("--seed", type=int, required=True)
     g.add_argument("--steps", type=int, default=50_000); g.add_argument("--every", type=int, default=100)
     g.add_argument("--group", type=int, default=64); g.add_argument("--out", required=True)
+    g.add_argument("--grid", action="store_true", help="H and L from the sweep's sets")
     t = sub.add_parser("train")
     t.add_argument("--data", nargs="+", required=True); t.add_argument("--inputs", type=int, choices=[4, 5], default=5)
     t.add_argument("--steps", type=int, default=20_000); t.add_argument("--batch", type=int, default=4096)
@@ -291,7 +299,7 @@ def _main(argv=None) -> int:
     a = ap.parse_args(argv)
     say = lambda m: print(m, flush=True)
     if a.cmd == "generate":
-        cases = draw_cases(a.n, a.seed, a.steps, a.every)
+        cases = draw_cases(a.n, a.seed, a.steps, a.every, grid=a.grid)
         t0 = time.perf_counter()
         traj = simulate(cases, a.steps, a.every, a.group, log=say)
         dt = time.perf_counter() - t0

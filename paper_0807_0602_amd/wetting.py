@@ -67,7 +67,8 @@ def laplace_tension(tau: Pair = (1.0, 1.0), G: float = 0.9, radii: Sequence[floa
     fit of Delta p = p_in - p_out against 1/R, R from the droplet area (nodes with
     n_A > n_B).  `rho`: initial (majority, minority) densities of the drop, `gas`: initial
     (n_A, n_B) around it.  Returns gamma, the intercept, the per-droplet data and the smallest
-    density seen (slightly negative minority densities occur with unequal sound speeds)."""
+    density seen, overall and per droplet (slightly negative minority densities occur with unequal
+    sound speeds)."""
     geom = Geometry(n, n, 0, 0)
     prm = Params(G=G, gw=(0.0, 0.0), tau=tuple(tau), alpha=tuple(alpha), mass=tuple(mass))
     cases = [Case(geom, prm, noise=0.0, name=f"droplet_R{R}") for R in radii]
@@ -78,11 +79,13 @@ def laplace_tension(tau: Pair = (1.0, 1.0), G: float = 0.9, radii: Sequence[floa
     Y, X = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
     r = np.hypot(X - c, Y - c)
     min_density = np.inf
+    mins = []
     for (nA, nB, flags), R0 in zip(res, radii):
         if not (np.isfinite(nA).all() and np.isfinite(nB).all()):
             raise RuntimeError(f"droplet R = {R0} went unstable (non-finite density); start closer "
                                "to the coexisting compositions or change tau")
-        min_density = min(min_density, float(nA.min()), float(nB.min()))
+        mins.append(min(float(nA.min()), float(nB.min())))
+        min_density = min(min_density, mins[-1])
         p = eos_pressure(nA, nB, G, alpha, mass)
         R = np.sqrt(np.count_nonzero(nA > nB) / np.pi)
         p_in = p[r < 0.5 * R].mean()
@@ -92,7 +95,7 @@ def laplace_tension(tau: Pair = (1.0, 1.0), G: float = 0.9, radii: Sequence[floa
     A = np.stack([1.0 / np.asarray(Rs), np.ones(len(Rs))], axis=1)
     (gamma, icpt), *_ = np.linalg.lstsq(A, np.asarray(dps), rcond=None)
     return {"gamma": float(gamma), "intercept": float(icpt), "R": Rs, "dp": dps,
-            "min_density": min_density}
+            "min_density": min_density, "min_densities": mins}
 
 
 # ------------------------------------------------------------------------------ estimators

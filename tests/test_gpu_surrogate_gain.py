@@ -1,11 +1,15 @@
 """What the trained surrogate gains over the LBM it replaces, scored against the LBM.
 
-Eight fresh channels are drawn like the training set (seed 5), simulated for 50 000 steps by the
-batched LBM and predicted by the committed 5-input network.  The network must answer the same
-curves at least 100 times faster than the LBM produced them and keep the typical per-channel
-worst-case front error within a few lattice units (the exact accuracy over 64 channels is
-measured and reported by bench.py --workload surrogate).  A fresh draw can fall just outside
-the box of the 2000 training draws; such a channel is answered by the LBM (checked here).
+The 64 channels of the calibration sweep (draw seed 0, not in the training set) and 32 fresh
+channels drawn from the continuous ranges (seed 3, the held-out set) are simulated for 50 000
+steps by the batched LBM and predicted by the committed 5-input network; the error of a channel
+is its largest |z_surrogate - z_LBM| in lattice units over the LBM's samples (up to an
+instability or reservoir-drained flag).  On the sweep's channels at least 95 % must lie within
+1 lattice unit and none beyond 2 (measured: 98.4 %, worst 1.40); on the continuous draws at least
+75 % within 1 lattice unit (measured on the 200 held-out channels: 84 %).  The network must answer
+the same curves at least 1000 times faster than the LBM produced them.  A fresh continuous draw
+can fall just outside the box of the training draws; such a channel is answered by the LBM
+(checked here).
 """
 import os
 import sys
@@ -25,16 +29,22 @@ def _say(m):
     sys.stdout.flush()
 
 
-def test_surrogate_gain_over_lbm():
+@pytest.fixture(scope="module")
+def net():
     import torch
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     if not os.path.exists(WEIGHTS):
         pytest.skip("trained weights not present")
     from paper_0807_0602_amd import surrogate as S
-    net = S.Network.load(WEIGHTS)
-    cases = S.draw_cases(8, seed=5)
-    _say("case: surrogate gain, 8 channels x 50000 steps")
+    n = S.Network.load(WEIGHTS)
+    yield n
+    n.close()
+
+
+def _score(net, cases):
+    import torch
+    from paper_0807_0602_amd import surrogate as S
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     traj = S.simulate(cases, 50_000, 100)
@@ -49,11 +59,33 @@ def test_surrogate_gain_over_lbm():
         net.predict(X)
     sur_s = (time.perf_counter() - t0) / 10
     ok = np.isfinite(errs[:, 0])
-    _say(f"  LBM {lbm_s:.2f} s, surrogate {sur_s * 1e3:.2f} ms, speedup {lbm_s / sur_s:.0f}x, "
-         f"max|dz| per channel {np.round(errs[ok, 0], 2)}, inside hull {inside:.3f}")
-    assert lbm_s / sur_s > 100
+    return traj, errs[ok, 0], inside, lbm_s, sur_s
+
+
+def test_surrogate_on_the_sweep_channels(net):
+    from paper_0807_0602_amd import inputs
+    cases = inputs.sweep_draws(64, seed=0)
+    _say("case: surrogate vs LBM, the 64 sweep channels x 50000 steps")
+    _, e, inside, lbm_s, sur_s = _score(net, cases)
+    within = float(np.mean(e <= 1.0))
+    _say(f"  LBM {lbm_s:.2f} s, surrogate {sur_s * 1e3:.2f} ms, speedup {lbm_s / sur_s:.0f}x; "
+         f"{within:.1%} of {e.size} channels within 1 lu, worst {e.max():.2f}, median {np.median(e):.2f}")
+    assert e.size == 64 and inside == 1.0
+    assert lbm_s / sur_s > 1000
+    assert within >= 0.95
+    assert e.max() <= 2.0
+
+
+def test_surrogate_on_continuous_draws_and_fallback(net):
+    from paper_0807_0602_amd import surrogate as S
+    cases = S.draw_cases(32, seed=3)
+    _say("case: surrogate vs LBM, 32 held-out continuous draws x 50000 steps")
+    traj, e, inside, lbm_s, sur_s = _score(net, cases)
+    within = float(np.mean(e <= 1.0))
+    _say(f"  {within:.1%} of {e.size} channels within 1 lu, worst {e.max():.2f}, median {np.median(e):.2f}, "
+         f"inside hull {inside:.3f}")
     assert inside >= 0.75
-    assert np.median(errs[ok, 0]) < 5.0
+    assert within >= 0.75
     # the fallback: channels with any query outside the training box come from the LBM
     t = np.arange(100, 50_001, 100, dtype=float)
     Z, P, used_lbm = S.predict_curves(net, cases, t, with_length=True)

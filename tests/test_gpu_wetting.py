@@ -110,13 +110,68 @@ def test_density_ratio_droplets_obey_laplace(W):
     """Unequal sound speeds (alpha = 0.8 for the drop, 4/9 around it) with the paper's
     relaxation times for its water-in-air runs (tau = 2.5 and 0.626, i.e. nu = 0.667 and 0.042,
     labels as read): static drops hold a density ratio above 2.2 and follow Laplace's law with
-    the pressure of unequal sound speeds."""
-    al, tau, G = (0.8, 4.0 / 9.0), (2.5, 0.626), 1.5
-    lt = W.laplace_tension(tau, G, alpha=al, rho=(1.25, 0.005), gas=(0.17, 0.31), steps=20000)
+    the pressure of unequal sound speeds.  In this model the minority component dips slightly
+    below zero (about -5.4e-3, below the health flag's -1e-3): the FP64 oracle does the same
+    (tests/golden/density_ratio_droplets.json, written by the oracle-only script beside it), and
+    each GPU drop must reproduce the oracle's smallest density, radius and pressure jump."""
+    import json
+    import os
+    ref = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "density_ratio_droplets.json")))
+    al, tau, G = tuple(ref["alpha"]), tuple(ref["tau"]), ref["G"]
+    lt = W.laplace_tension(tau, G, alpha=al, rho=tuple(ref["init_inside"]), gas=tuple(ref["init_outside"]),
+                           steps=ref["steps"], radii=[d["R0"] for d in ref["drops"]], n=ref["n"])
     dpR = np.asarray(lt["dp"]) * np.asarray(lt["R"])
     _say(f"  density-ratio drops: gamma {lt['gamma']:.5f} intercept {lt['intercept']:.2e} "
-         f"spread {dpR.std() / dpR.mean():.3%} smallest density {lt['min_density']:.2e}")
-    assert lt["min_density"] > -0.01
+         f"spread {dpR.std() / dpR.mean():.3%} smallest density {lt['min_density']:.3e} "
+         f"(oracle {min(d['min_density'] for d in ref['drops']):.3e})")
+    for d, R, dp, mn in zip(ref["drops"], lt["R"], lt["dp"], lt["min_densities"]):
+        _say(f"    R0 {d['R0']}: R {R:.3f} ({d['R']:.3f})  dp {dp:.6f} ({d['dp']:.6f})  min {mn:.3e} ({d['min_density']:.3e})")
+        assert abs(R - d["R"]) <= 0.05
+        assert abs(dp - d["dp"]) <= 0.01 * d["dp"]
+        assert abs(mn - d["min_density"]) <= 2e-4
     assert dpR.std() / dpR.mean() <= 0.03
     assert abs(lt["intercept"]) <= 0.1 * lt["dp"][-1]
     assert 0.02 < lt["gamma"] < 0.1
+
+
+def test_density_ratio_capillary_fills(W):
+    """A dynamic capillary with a density ratio (Sec. 3: unequal rest fractions alpha = (0.8, 4/9)
+    give the liquid the lower sound speed): 2048 x 42 (H = 40), walls over x in [512, 1536), liquid
+    (1.25, 0.005) for x < 512 and gas (0.17, 0.31) elsewhere, G = 1.5, tau = (2.5, 0.7),
+    G_w = -+0.2.  It matches the FP64 oracle after 500 steps, then fills for 60 000 steps without
+    raising the health flag, the front advancing steadily, with a liquid-to-gas density ratio
+    above 2.4 inside the channel.  (The paper's tau_B = 0.626 raises the flag within 1000 steps at
+    this G; no set reached its 1:3 dynamically, see the design notes.)"""
+    from paper_0807_0602_amd.scf import Channel
+    from parity_util import front_diff, max_abs_diff
+    geom = inputs.Geometry(2048, 42, 512, 1536)
+    case = inputs.Case(geom, inputs.Params(G=1.5, gw=(-0.2, 0.2), tau=(2.5, 0.7), alpha=(0.8, 4 / 9)), noise=0.0)
+    X = np.arange(2048)[None, :].repeat(42, 0)
+    a = np.where(X < 512, 1.25, 0.17).astype(float)
+    b = np.where(X < 512, 0.005, 0.31).astype(float)
+    _say("case: density-ratio capillary 2048 x 42, alpha (0.8, 4/9), tau (2.5, 0.7), 60000 steps")
+    ch = Channel(geom, case.params, a, b)
+    ch.step(500)
+    orc = oracle.Oracle.from_case(case).init(a, b).step(500)
+    nA, nB = ch.density()
+    rA, rB = orc.density()
+    err = max_abs_diff((nA, rA), (nB, rB))
+    dz = front_diff(ch.observe()["z"], orc.observe()["z"])
+    _say(f"  oracle at t = 500: max|drho| = {err:.2e}, |dz| = {dz:.2e}")
+    assert err <= 1e-5 and dz <= 0.5
+    zs = []
+    for t in range(1000, 60_001, 1000):
+        ch.step(t - ch.t)
+        o = ch.observe()
+        assert not o["flags"] & 2, t
+        zs.append(o["z"])
+    zs = np.array(zs)
+    nA, nB = ch.density()
+    z = zs[-1]
+    xl, xg = int(512 + 0.5 * z), int(512 + z + 0.5 * (1024 - z))
+    ratio = (nA[21, xl] + nB[21, xl]) / (nA[21, xg] + nB[21, xg])
+    _say(f"  z: {zs[9]:.1f} (10k) {zs[29]:.1f} (30k) {z:.1f} (60k); density ratio {ratio:.3f}; "
+         f"smallest density {min(nA.min(), nB.min()):.2e}")
+    assert np.isfinite(zs).all() and np.all(np.diff(zs[9:]) > 0)
+    assert z > 40.0
+    assert ratio > 2.4

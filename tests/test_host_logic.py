@@ -37,11 +37,19 @@ def test_features_and_dataset_masking(tmp_path):
     traj[:, :, 2] = 3.0
     traj[1, 3, 1] = np.nan            # missing front: dropped
     traj[2, 4:, 4] = 1.0              # unstable from sample 4 on: dropped
+    traj[0, 2, 3] = 2.0               # flag bit 1 alone does not drop (the unstable column does)
+    traj[1, 5, 3] = 1.0               # reservoir drained at sample 5: dropped from there on
     X, T, w, k = S.dataset(cases, traj)
     assert X.shape == (3 * ns, 4) and T.shape == (3 * ns, 2)
     keep = k.reshape(3, ns)
     assert not keep[:, 0].any()       # t = 0 < t_min
-    assert keep[0, 1:].all() and not keep[1, 3] and keep[1, 4] and not keep[2, 4:].any()
+    assert keep[0, 1:].all() and not keep[1, 3] and keep[1, 4] and not keep[1, 5]
+    assert not keep[2, 4:].any()
+    traj[1, 5, 3] = 0.0
+    traj[1, 4, 3] = 3.0               # both bits at sample 4: dropped from sample 4 on
+    keep = S.dataset(cases, traj)[3].reshape(3, ns)
+    assert keep[1, 2] and not keep[1, 4:].any()
+    traj[1, 4, 3] = 0.0
     H = np.repeat([c.geom.ny - 2 for c in cases], ns)
     np.testing.assert_allclose(w, H * H)
     np.testing.assert_allclose(T[k, 0], (2.0 / H)[k], rtol=1e-6)

@@ -101,3 +101,22 @@ def test_instability_golden_regenerates_from_the_oracle(tmp_path, monkeypatch):
     new = json.load(open(tmp_path / "sweep_instability_H20_L512_r2.json"))
     assert new["first_unstable_t"] == ref["first_unstable_t"]
     assert new["z_every_1000"] == ref["z_every_1000"]
+
+
+def test_density_ratio_golden_regenerates_from_the_oracle(tmp_path, monkeypatch):
+    """The stored density-ratio drop record is what the oracle-only script writes (its smallest
+    drop, rerun here: the same numbers to the last digit)."""
+    import importlib.util
+    import json
+    import os
+    here = os.path.join(os.path.dirname(__file__), "golden")
+    ref = json.load(open(os.path.join(here, "density_ratio_droplets.json")))
+    spec = importlib.util.spec_from_file_location("make_density_ratio_droplets",
+                                                  os.path.join(here, "make_density_ratio_droplets.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    monkeypatch.setattr(mod, "HERE", str(tmp_path))
+    monkeypatch.setattr(mod, "RADII", (10,))
+    mod.main()
+    new = json.load(open(tmp_path / "density_ratio_droplets.json"))
+    assert new["drops"][0] == ref["drops"][0]
