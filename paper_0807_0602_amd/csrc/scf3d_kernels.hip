@@ -384,24 +384,39 @@ k3_pull_out(const Chan3* __restrict__ cp, float* __restrict__ ws, int src) {
 }
 
 // Observables from the density field (k3_density first): FP64 mass per (y, z) row and a health
-// flag, then one block sums the rows in order and finds the centre-line front.
+// flag, then one block sums the rows in order and finds the centre-line front.  Block reductions
+// run in a fixed order: a butterfly over each wave's 64 lanes, then the wave results through LDS.
+constexpr int kWaves = kThreads / 64;
+
 template <typename T>
 __device__ __forceinline__ T bsum(T v, T* sh) {
-    sh[threadIdx.x] = v;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
     __syncthreads();
-    for (int s = kThreads / 2; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
-        __syncthreads();
-    }
-    const T r = sh[0];
+    T r = sh[0];
+#pragma unroll
+    for (int w = 1; w < kWaves; ++w) r += sh[w];
+    __syncthreads();
+    return r;
+}
+
+__device__ __forceinline__ int bmin(int v, int* sh) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = min(v, __shfl_xor(v, off, 64));
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    int r = sh[0];
+#pragma unroll
+    for (int w = 1; w < kWaves; ++w) r = min(r, sh[w]);
     __syncthreads();
     return r;
 }
 
 __global__ void __launch_bounds__(kThreads)
 k3_obs_rows(const Chan3* __restrict__ cp, const float* __restrict__ ws, Part3* __restrict__ parts) {
-    __shared__ double sd[kThreads];
-    __shared__ int si[kThreads];
+    __shared__ double sd[kWaves];
+    __shared__ int si[kWaves];
     const Chan3 c = *cp;
     const int y = blockIdx.x, z = blockIdx.y;
     const float* __restrict__ nAf = ws + c.off + 76 * c.plane;
@@ -431,8 +446,8 @@ k3_obs_rows(const Chan3* __restrict__ cp, const float* __restrict__ ws, Part3* _
 __global__ void __launch_bounds__(kThreads)
 k3_obs_final(const Chan3* __restrict__ cp, const float* __restrict__ ws, const Part3* __restrict__ parts,
              Obs3* __restrict__ out) {
-    __shared__ double sd[kThreads];
-    __shared__ int si[kThreads];
+    __shared__ double sd[kWaves];
+    __shared__ int si[kWaves];
     const Chan3 c = *cp;
     const int tid = threadIdx.x;
     const float* __restrict__ nAf = ws + c.off + 76 * c.plane;
@@ -461,13 +476,7 @@ k3_obs_final(const Chan3* __restrict__ cp, const float* __restrict__ ws, const P
     const int xs0 = c.x0 / 2;
     for (int x = xs0 + tid; x + 1 < c.nx; x += kThreads)
         if (xz == big && phi(x) >= 0.0 && phi(x + 1) < 0.0) xz = x;
-    si[tid] = xz;
-    __syncthreads();
-    for (int s = kThreads / 2; s > 0; s >>= 1) {
-        if (tid < s) si[tid] = min(si[tid], si[tid + s]);
-        __syncthreads();
-    }
-    xz = si[0];
+    xz = bmin(xz, si);
     if (tid == 0) {
         Obs3 o;
         o.t = 0;

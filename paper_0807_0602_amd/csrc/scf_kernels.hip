@@ -764,29 +764,43 @@ k_pull_out(const Chan* __restrict__ chans, const RowRef* __restrict__ rows, floa
 // channel): the row sums in fixed order, then the centre-line front and the wall-row film
 // fronts by a parallel first-crossing search.  Both passes are deterministic.
 // ---------------------------------------------------------------------------------------------
+// Block reductions in a fixed order (results are bit-reproducible): a butterfly over the 64 lanes
+// of each wave by cross-lane swaps, then the kRowThreads / 64 wave results through LDS, summed by
+// every thread in wave order.  Two barriers per reduction.
+constexpr int kRowWaves = kRowThreads / 64;
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+__device__ __forceinline__ int wave_min(int v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = min(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
 template <typename T>
 __device__ __forceinline__ T block_sum(T v, T* scratch) {
-    const int tid = threadIdx.x;
-    scratch[tid] = v;
+    v = wave_sum(v);
+    if ((threadIdx.x & 63) == 0) scratch[threadIdx.x >> 6] = v;
     __syncthreads();
-    for (int s = kRowThreads / 2; s > 0; s >>= 1) {
-        if (tid < s) scratch[tid] += scratch[tid + s];
-        __syncthreads();
-    }
-    const T r = scratch[0];
+    T r = scratch[0];
+#pragma unroll
+    for (int w = 1; w < kRowWaves; ++w) r += scratch[w];
     __syncthreads();
     return r;
 }
 
 __device__ __forceinline__ int block_min(int v, int* scratch) {
-    const int tid = threadIdx.x;
-    scratch[tid] = v;
+    v = wave_min(v);
+    if ((threadIdx.x & 63) == 0) scratch[threadIdx.x >> 6] = v;
     __syncthreads();
-    for (int s = kRowThreads / 2; s > 0; s >>= 1) {
-        if (tid < s) scratch[tid] = min(scratch[tid], scratch[tid + s]);
-        __syncthreads();
-    }
-    const int r = scratch[0];
+    int r = scratch[0];
+#pragma unroll
+    for (int w = 1; w < kRowWaves; ++w) r = min(r, scratch[w]);
     __syncthreads();
     return r;
 }
@@ -794,8 +808,8 @@ __device__ __forceinline__ int block_min(int v, int* scratch) {
 __global__ void __launch_bounds__(kRowThreads)
 k_obs_rows(const Chan* __restrict__ chans, const RowRef* __restrict__ rows, float* __restrict__ ws,
            int src, RowPartial* __restrict__ part) {
-    __shared__ double sd[kRowThreads];
-    __shared__ int si[kRowThreads];
+    __shared__ double sd[kRowWaves];
+    __shared__ int si[kRowWaves];
     const RowRef r = rows[blockIdx.x];
     const Chan c = chans[r.chan];
     const float* __restrict__ g = ws + c.off + (int64_t)src * 18 * c.plane;
@@ -838,8 +852,8 @@ __global__ void __launch_bounds__(kRowThreads)
 k_obs_final(const Chan* __restrict__ chans, const float* __restrict__ ws,
             const RowPartial* __restrict__ part, ObsRec* __restrict__ now, ObsRec* __restrict__ ring,
             const int32_t* __restrict__ counter, int max_samples, int record) {
-    __shared__ double sd[kRowThreads];
-    __shared__ int si[kRowThreads];
+    __shared__ double sd[kRowWaves];
+    __shared__ int si[kRowWaves];
     const int ch = blockIdx.x;
     const Chan c = chans[ch];
     const int tid = threadIdx.x;

@@ -59,6 +59,40 @@ def test_unequal_sound_speeds_flat_interface():
     assert abs(p(la, lb, eq) - p(ga, gb, eq)) > 0.05 * p(la, lb, eq)
 
 
+@pytest.mark.slow
+def test_density_ratio_bound_unequal_sound_speeds():
+    """How far the rest fractions alone separate the densities (Sec. 3, alpha = (0.8, 4/9),
+    m = 1).  Equal pressures across a flat interface, p = sum_k n_k c_k^2 + (G/3) n_A n_B with
+    c_k^2 = 3(1 - alpha_k)/5, give c_A^2 (l_A + l_B) <= p_liquid = p_gas
+    <= c_B^2 (g_A + g_B) + (G/3) g_A g_B, so the ratio R = (l_A + l_B)/(g_A + g_B) of the
+    coexisting phases is bounded by c_B^2/c_A^2 = 25/9 plus a term in the gas phase's minority
+    density.  A stronger coupling purifies the phases and raises R towards that bound; at G = 2 it
+    is above 2.55 with every density still above the health bound -1e-3 (at G = 2.5 the slab's
+    minority density falls to -0.018), so a ratio of 3 is out of reach for this pair at m = 1."""
+    nx, ny = 128, 4
+    al, m = (0.8, 4.0 / 9.0), (1.0, 1.0)
+    cA2, cB2 = 3 * (1 - al[0]) / 5, 3 * (1 - al[1]) / 5
+    X = np.arange(nx)[None, :].repeat(ny, 0)
+    liq = (X >= 32) & (X < 96)
+    oracle.set_threads(8)
+    ratios = []
+    for G in (1.5, 2.0):
+        a = np.where(liq, 1.0, 0.05).astype(float)
+        b = np.where(liq, 0.05, 0.34).astype(float)
+        o = oracle.Oracle(nx, ny, 0, 0, G, (0.0, 0.0), (1.0, 1.0), alpha=al, mass=m).init(a, b)
+        o.step(20000)
+        A, B = o.density()
+        assert np.isfinite(A).all() and np.isfinite(B).all()
+        assert min(A.min(), B.min()) > -1e-3
+        la, lb, ga, gb = A[0, 64], B[0, 64], A[0, 0], B[0, 0]
+        R = (la + lb) / (ga + gb)
+        bound = cB2 / cA2 + (G / 3) * ga * gb / (cA2 * (ga + gb))
+        assert R < bound
+        ratios.append(R)
+    assert ratios[1] > ratios[0] and ratios[1] > 2.55
+    assert ratios[1] < 25.0 / 9.0
+
+
 def test_unequal_masses_flat_interface():
     """Components of unequal molecular mass (rho_k = m_k n_k, Sec. 2; m = (1, 1.5)) across a
     flat interface at rest: the momentum flux of component k is m_k n_k c_s^2 while the forces of
