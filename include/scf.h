@@ -95,11 +95,12 @@ typedef struct {
                              band), optionally | SCF_ORDER_XCD (each of the 8 XCDs takes a
                              contiguous eighth of that order instead of every 8th tile).
                              SCF_ORDER_PERSIST (| SCF_ORDER_XCD) instead launches one block per
-                             resident slot (CUs x the kernel's occupancy) and gives each block one
-                             equal, contiguous range of the sequence of (channel, strip, row),
-                             split into tiles at strip ends (cy is then not used; ranges are at
-                             least 16 rows); with SCF_ORDER_XCD each XCD takes a contiguous
-                             eighth of the ranges */
+                             resident slot (CUs x the kernel's occupancy, or blocks_per_cu) and
+                             gives each block a contiguous run of the (channel, band, strip) tile
+                             list, the runs balanced by rows: each channel's rows are cut into
+                             round(ny / target) bands, with the band height `target` (from 16
+                             rows up) that minimises the largest run (cy is then not used); with
+                             SCF_ORDER_XCD each XCD takes a contiguous eighth of the runs */
     int32_t graph_steps;  /* steps per captured HIP graph, 0 = launch every step directly */
     int32_t fuse;         /* time steps per pass of the fused step: 1, or 2 (temporal blocking:
                              each launch advances two steps, its tiles are bx - 6 columns wide,

@@ -38,13 +38,13 @@ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 int pitch_of(int nx) { return (nx + 63) / 64 * 64; }
 
 constexpr int kMaxRowsPerGeom = 1 << 20;
-// Persistent schedules: at most this many blocks per launch, and ranges of at least kMinRange
-// rows (each range pays the pipeline's start-up rows once).
+// Persistent schedules: at most this many blocks per launch, and bands of at least kMinRange
+// rows where a channel is taller (each band pays the pipeline's start-up rows once).
 constexpr int kMaxPersistBlocks = 8192;
 constexpr int kMinRange = 16;
 // Version of the schedule space and kernels in the autotuner cache key (a cached schedule from
 // another version is timed again).
-constexpr int kTuneVersion = 4;
+constexpr int kTuneVersion = 5;
 constexpr int kPlanesPerChannel = 38;   // 2 x 18 population planes + 2 density planes
 
 // Float planes of one channel: populations and densities, plus one for the uint16 codes of a
@@ -261,40 +261,15 @@ struct Engine {
         return out;
     }
 
-    // Persistent schedule over strips `stripw` wide for `nblocks` blocks, at most one tile per
-    // block, so the whole step runs in one round with the tallest bands that fit: every channel's
-    // rows are cut into k_c near-equal bands with k_c = ceil(ny_c / R), R the smallest band
-    // height (>= kMinRange) for which the tiles, strips x bands summed over channels, number at
-    // most nblocks.  Bands are aligned across the strips of a channel and tiles are listed by
-    // (channel, band, strip), so horizontally adjacent tiles run at the same time and share the
-    // cache lines at their edges.  With SCF_ORDER_XCD (nblocks a multiple of 8) XCD x takes the
-    // x-th contiguous eighth of the list: block b, on XCD b mod 8, runs tile
-    // floor(T (b mod 8) / 8) + b / 8 of its eighth.  Odd bands walk downward in the single-step
-    // kernel, so two bands meet at their shared rows.  first[b] indexes block b's tile.
-    void make_tiles_persist(int stripw, int nblocks, int ord, std::vector<scf::TileDesc>& tl,
-                            std::vector<int32_t>& first) const {
-        std::vector<int> nstrip(nchan);
-        int maxny = 1;
-        for (int c = 0; c < nchan; ++c) {
-            nstrip[c] = (geom[c].nx + stripw - 1) / stripw;
-            maxny = std::max(maxny, geom[c].ny);
-        }
-        auto count = [&](int R) {
-            int64_t T = 0;
-            for (int c = 0; c < nchan; ++c) T += (int64_t)nstrip[c] * ((geom[c].ny + R - 1) / R);
-            return T;
-        };
-        int lo = std::min(kMinRange, maxny), hi = maxny;   // count(maxny) = number of strips
-        while (lo < hi) {
-            const int mid = (lo + hi) / 2;
-            if (count(mid) <= nblocks) hi = mid; else lo = mid + 1;
-        }
-        const int R = lo;
+    // (channel, band, strip) tiles over strips `stripw` wide, k_c = max(1, round(ny_c / target))
+    // near-equal bands per channel, aligned across the channel's strips; odd bands walk downward.
+    void band_tiles(int stripw, double target, std::vector<scf::TileDesc>& tl) const {
         tl.clear();
         for (int c = 0; c < nchan; ++c) {
-            const int ny = geom[c].ny, k = (ny + R - 1) / R;
+            const int ny = geom[c].ny, ns = (geom[c].nx + stripw - 1) / stripw;
+            const int k = std::max(1, (int)std::lround(ny / target));
             for (int j = 0; j < k; ++j)
-                for (int s_ = 0; s_ < nstrip[c]; ++s_) {
+                for (int s_ = 0; s_ < ns; ++s_) {
                     scf::TileDesc td;
                     std::memset(&td, 0, sizeof td);
                     td.chan = c;
@@ -306,29 +281,95 @@ struct Engine {
                     tl.push_back(td);
                 }
         }
-        // more strips than blocks (R = maxny still too many): blocks take several tiles each
-        const int64_t T = (int64_t)tl.size();
+    }
+
+    // Cost of a tile in quarter rows: 4 per row it outputs plus `warm` for the pipeline's start-up
+    // rows (2 for one step per pass, 6 for two; a start-up row does about a quarter of a row's
+    // work).  Greedy packing of the list, in order and whole tiles only, into blocks of capacity
+    // `cap`; returns the blocks used and, with `starts`, each block's first tile.
+    static int64_t tile_cost(const scf::TileDesc& t, int warm) { return 4 * (int64_t)(t.ye - t.yb) + warm; }
+    static int pack_tiles(const std::vector<scf::TileDesc>& tl, int64_t cap, int warm,
+                          std::vector<int32_t>* starts) {
+        int nb = 0;
+        int64_t cur = cap + 1;
+        for (size_t t = 0; t < tl.size(); ++t) {
+            const int64_t w = tile_cost(tl[t], warm);
+            if (cur + w > cap) {
+                ++nb;
+                cur = 0;
+                if (starts) starts->push_back((int32_t)t);
+            }
+            cur += w;
+        }
+        return nb;
+    }
+
+    // Persistent schedule over strips `stripw` wide for `nblocks` blocks (one round: every block
+    // resident at once).  Each block runs a contiguous run of the (channel, band, strip) list, so
+    // horizontally adjacent tiles run at the same time and share the cache lines at their edges.
+    // The runs are balanced by work, not by tile count: for a band height `target` (a geometric
+    // grid from kMinRange to the tallest channel) every channel gets k_c = round(ny_c / target)
+    // bands, the smallest block capacity that packs the list into nblocks runs is found by
+    // bisection, and the target with the smallest capacity wins (ties: the taller bands).  A
+    // single channel thus gets the tallest bands that give one tile per block; channels of
+    // unequal height and length share the blocks by their rows.  With SCF_ORDER_XCD (nblocks a
+    // multiple of 8) XCD x takes the x-th contiguous eighth of the runs, spread evenly over its
+    // slots b = x, x + 8, ...  first[b] .. first[b+1] index block b's tiles.
+    void make_tiles_persist(int stripw, int warm, int nblocks, int ord, std::vector<scf::TileDesc>& tl,
+                            std::vector<int32_t>& first) const {
+        int maxny = 1;
+        for (int c = 0; c < nchan; ++c) maxny = std::max(maxny, geom[c].ny);
+        auto min_cap = [&](const std::vector<scf::TileDesc>& t) {
+            int64_t lo = 0, hi = 0;
+            for (const scf::TileDesc& d : t) {
+                lo = std::max(lo, tile_cost(d, warm));
+                hi += tile_cost(d, warm);
+            }
+            hi = std::max(hi, lo);
+            while (lo < hi) {
+                const int64_t mid = lo + (hi - lo) / 2;
+                if (pack_tiles(t, mid, warm, nullptr) <= nblocks) hi = mid; else lo = mid + 1;
+            }
+            return lo;
+        };
+        std::vector<scf::TileDesc> t0;
+        int64_t best = -1;
+        double best_target = maxny;
+        for (double target = std::min(kMinRange, maxny);; target *= 1.04) {
+            const double tg = std::min(target, (double)maxny);
+            band_tiles(stripw, tg, t0);
+            const int64_t c = min_cap(t0);
+            if (best < 0 || c <= best) {
+                best = c;
+                best_target = tg;
+            }
+            if (tg >= maxny) break;
+        }
+        band_tiles(stripw, best_target, t0);
+        std::vector<int32_t> starts;
+        const int nb = pack_tiles(t0, best, warm, &starts);
+        starts.push_back((int32_t)t0.size());
+        // run j of the nb runs goes to block b; with the XCD order, XCD x's runs
+        // [nb x / 8, nb (x + 1) / 8) are spread evenly over its nblocks / 8 slots
         const bool xcd = (ord & SCF_ORDER_XCD) && nblocks % 8 == 0;
+        tl.clear();
         first.assign((size_t)nblocks + 1, 0);
-        std::vector<scf::TileDesc> out;
-        out.reserve(tl.size());
         for (int b = 0; b < nblocks; ++b) {
-            first[b] = (int32_t)out.size();
-            // block b's share [t0, t1) of the list
-            int64_t t0, t1;
+            first[b] = (int32_t)tl.size();
+            int64_t j0, j1;
             if (xcd) {
                 const int x = b % 8, i = b / 8, per = nblocks / 8;
-                const int64_t e0 = T * x / 8, e1 = T * (x + 1) / 8;   // XCD x's eighth
-                t0 = e0 + (e1 - e0) * i / per;
-                t1 = e0 + (e1 - e0) * (i + 1) / per;
+                const int64_t e0 = (int64_t)nb * x / 8, e1 = (int64_t)nb * (x + 1) / 8;
+                j0 = e0 + (e1 - e0) * i / per;
+                j1 = e0 + (e1 - e0) * (i + 1) / per;
             } else {
-                t0 = T * b / nblocks;
-                t1 = T * (b + 1) / nblocks;
+                j0 = (int64_t)nb * b / nblocks;
+                j1 = (int64_t)nb * (b + 1) / nblocks;
             }
-            for (int64_t t = t0; t < t1; ++t) out.push_back(tl[(size_t)t]);
+            for (int64_t j = j0; j < j1; ++j)
+                for (int32_t t = starts[(size_t)j]; t < starts[(size_t)j + 1]; ++t) tl.push_back(t0[(size_t)t]);
         }
-        first[nblocks] = (int32_t)out.size();
-        tl.swap(out);
+        first[nblocks] = (int32_t)tl.size();
     }
 
     // Blocks of a persistent launch: every CU filled to the kernel's occupancy (a multiple of 8
@@ -355,8 +396,8 @@ struct Engine {
             g1 = persist_blocks(bxv, 1, ord);
             g2 = persist_blocks(bxv, 2, ord);
             if (!g1 || !g2) return fail(SCF_EDEVICE, "occupancy query for the persistent schedule failed");
-            make_tiles_persist(bxv, g1, ord, tl, f1);
-            make_tiles_persist(strip2(bxv), g2, ord, tl2, f2);
+            make_tiles_persist(bxv, 2, g1, ord, tl, f1);
+            make_tiles_persist(strip2(bxv), 6, g2, ord, tl2, f2);
         } else {
             tl = make_tiles(bxv, cyv, ord);
             tl2 = make_tiles(strip2(bxv), cyv, ord);

@@ -1,8 +1,9 @@
-"""Persistent schedules (SCF_ORDER_PERSIST): one block per resident slot, each walking one equal,
-contiguous range of (channel, strip, row).  They change only which block computes which node, so
-every persistent schedule must reproduce the default schedule bit for bit, one or two steps per
-launch, with and without graphs, on edge geometries, masks, batches of uneven channels and the
-full-size bench and sweep cases."""
+"""Persistent schedules (SCF_ORDER_PERSIST): one block per resident slot, each walking a
+contiguous run of the (channel, band, strip) tile list, the runs balanced by rows.  They change
+only which block computes which node, so every persistent schedule must reproduce the default
+schedule bit for bit, one or two steps per launch, with and without graphs, on edge geometries,
+masks, batches of uneven channels and the full-size bench and sweep cases (with one block per CU
+the sweep's blocks each run several tiles)."""
 import sys
 
 import numpy as np
@@ -107,17 +108,19 @@ def test_persistent_full_size_bitwise(scf, bx):
     torch.cuda.empty_cache()
 
 
-def test_persistent_full_size_sweep_bitwise(scf):
-    """The 64-channel sweep at its full size: persistent two-step schedule vs the row-band one."""
+@pytest.mark.parametrize("order,bpc", [(PERSIST | XCD, 0), (PERSIST, 1), (PERSIST | XCD, 1)])
+def test_persistent_full_size_sweep_bitwise(scf, order, bpc):
+    """The 64-channel sweep at its full size: persistent two-step schedule vs the row-band one;
+    with one block per CU (256 blocks for 755 strips) every block runs several tiles."""
     import torch
     cases = inputs.sweep_draws(64, seed=0)
-    _say("case: persistent 64-channel sweep full size, 6 steps")
+    _say(f"case: persistent 64-channel sweep full size, order={order} blocks_per_cu={bpc}, 6 steps")
     out = []
-    for order in (1, PERSIST | XCD):
+    for o, n in ((1, 0), (order, bpc)):
         b = scf.Batch(cases, sample_every=100, max_samples=2)
-        b.set_tile(256, 8, graph_steps=0, order=order, fuse=2)
+        b.set_tile(256, 8, graph_steps=0, order=o, fuse=2, blocks_per_cu=n)
         b.step(6)
-        out.append([b.density(i) for i in (0, 5, 27, 63)])
+        out.append([b.density(i) for i in (0, 5, 27, 40, 63)])
         del b
         torch.cuda.empty_cache()
     for (a0, a1), (b0, b1) in zip(*out):
