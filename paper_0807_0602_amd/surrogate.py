@@ -175,7 +175,7 @@ def simulate(cases: Sequence[Case], steps: int, every: int, group: int = 64, log
     for g0 in range(0, len(cases), group):
         part = list(cases[g0:g0 + group])
         b = Batch(part, sample_every=every, max_samples=ns)
-        b.set_tile(256, 16, every, 3, 2)   # two steps per launch (the sweep's autotuned schedule)
+        b.set_tile(256, 16, every, 6, 2)   # persistent, two steps per launch (the sweep's autotuned schedule)
         b.step(steps)
         recs, k = b.observe(allow_unstable=True)
         for c, r in enumerate(recs):
@@ -189,16 +189,33 @@ def simulate(cases: Sequence[Case], steps: int, every: int, group: int = 64, log
     return out
 
 
+def precursor_jumped(t: np.ndarray, p: np.ndarray) -> np.ndarray:
+    """True from the first sample at which the precursor moved farther than one node per step
+    since the previous sample where it was found (missing samples are skipped).  No front moves
+    faster than the lattice speed; such a jump is the precursor level (a third of the liquid
+    reservoir's density at its centre) dropping as the reservoir drains, one sample before the
+    drain flag, when the crossing search leaps to the far end of the channel."""
+    t = np.asarray(t, np.float64)
+    p = np.asarray(p, np.float64)
+    i = np.nonzero(np.isfinite(p))[0]
+    jump = np.zeros(p.shape, bool)
+    if i.size > 1:
+        jump[i[1:]] = np.abs(np.diff(p[i])) > np.diff(t[i])
+    return np.cumsum(jump) > 0
+
+
 def dataset(cases: Sequence[Case], traj: np.ndarray, with_length: bool = False, t_min: float = 100.0):
     """(X, T, w, keep): features, targets (z/H, p/H), weights H^2, and the mask of kept samples
-    (t >= t_min, finite z and p, no instability so far, and the liquid reservoir not yet drained
-    to its centre: from that flag on the film level is read in gas and the front is no longer
-    fed by a reservoir, so the samples no longer describe capillary filling)."""
+    (t >= t_min, finite z and p, no instability so far, and the liquid reservoir not yet drained:
+    from the drain flag on (the reservoir drained to its centre) the film level is read in gas and
+    the front is no longer fed by a reservoir, so the samples no longer describe capillary
+    filling; the drain shows one sample earlier as a precursor jump faster than the lattice
+    speed, see precursor_jumped)."""
     Xs, Ts, ws, keep = [], [], [], []
     for case, tr in zip(cases, traj):
         H = float(case.geom.ny - 2)
         t, z, p, flags, unst = tr[:, 0], tr[:, 1], tr[:, 2], tr[:, 3], tr[:, 4]
-        drained = np.cumsum((np.nan_to_num(flags).astype(np.int64) & 1) > 0) > 0
+        drained = (np.cumsum((np.nan_to_num(flags).astype(np.int64) & 1) > 0) > 0) | precursor_jumped(t, p)
         ok = (t >= t_min) & np.isfinite(z) & np.isfinite(p) & (unst == 0) & ~drained
         Xs.append(features(case, np.maximum(t, 1.0), with_length))
         Ts.append(np.stack([z / H, p / H], axis=1))

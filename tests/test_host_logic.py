@@ -50,6 +50,19 @@ def test_features_and_dataset_masking(tmp_path):
     keep = S.dataset(cases, traj)[3].reshape(3, ns)
     assert keep[1, 2] and not keep[1, 4:].any()
     traj[1, 4, 3] = 0.0
+    # a precursor faster than one node per step is the draining reservoir: dropped from there on;
+    # 90 nodes in 100 steps stays, and a missing precursor in between is skipped, not a jump
+    traj[0, 2, 2] = 93.0
+    traj[0, 3, 2] = np.nan
+    traj[0, 4, 2] = 183.0
+    traj[0, 5, 2] = 273.0
+    keep = S.dataset(cases, traj)[3].reshape(3, ns)
+    assert keep[0, 1] and keep[0, 2] and not keep[0, 3] and keep[0, 4] and keep[0, 5]
+    traj[0, 5, 2] = 500.0
+    keep = S.dataset(cases, traj)[3].reshape(3, ns)
+    assert keep[0, 4] and not keep[0, 5]
+    assert not S.precursor_jumped(traj[0, :, 0], traj[0, :, 2])[:5].any()
+    traj[0, 2:, 2] = 3.0
     H = np.repeat([c.geom.ny - 2 for c in cases], ns)
     np.testing.assert_allclose(w, H * H)
     np.testing.assert_allclose(T[k, 0], (2.0 / H)[k], rtol=1e-6)
