@@ -282,8 +282,11 @@ def score_surrogate(weights: str, cases, traj, lbm_wall: float, reps: int = 20) 
     net = S.Network.load(weights)
     wl = net.cfg.d_in == 5
     errs, inside = S.curve_errors(net, cases, traj, wl)
-    X, _, _, _ = S.dataset(cases, traj, wl)
-    net.predict(X)                        # warm-up
+    X, _, _, keep = S.dataset(cases, traj, wl)
+    _, in_hull = net.predict(X)           # also the warm-up
+    ns = traj.shape[1]
+    # channels with any kept query outside the training box: answered by the LBM
+    fallback = sum(1 for c in range(len(cases)) if not in_hull[c * ns:(c + 1) * ns][keep[c * ns:(c + 1) * ns]].all())
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(reps):
@@ -294,13 +297,22 @@ def score_surrogate(weights: str, cases, traj, lbm_wall: float, reps: int = 20) 
     within = float(np.mean(errs[ok, 0] <= 1.0)) if ok.any() else 0.0
     sur_pph = len(cases) * 3600.0 / sur_s
     lbm_pph = len(cases) * 3600.0 / lbm_wall
+    # one-off cost of the network (LBM data and training, GPU seconds, stored with the weights) and
+    # the number of answered curves after which it has cost less than the LBM would have
+    z = np.load(weights)
+    info = json.loads(str(z["info"])) if "info" in z.files else {}
+    train_s, data_s = info.get("seconds"), info.get("data_seconds")
+    cost = {"training_seconds": train_s, "data_seconds": data_s, "break_even_points": None}
+    if train_s is not None and data_s is not None:
+        cost["break_even_points"] = round((train_s + data_s) / 3600.0 / (1.0 / lbm_pph - 1.0 / sur_pph), 1)
     return {"inputs": int(net.cfg.d_in), "surrogate_points_per_hour": round(sur_pph, 1),
             "lbm_points_per_hour": round(lbm_pph, 1), "speedup": round(sur_pph / lbm_pph, 1),
             "scored_channels": int(ok.sum()), "fraction_within_1lu": round(within, 4),
             "points_per_hour_within_1lu": round(sur_pph * within, 1),
             "max_dz_lu": round(float(np.nanmax(errs[:, 0])), 4),
             "median_max_dz_lu": round(float(np.nanmedian(errs[:, 0])), 4),
-            "inside_training_hull": round(inside, 4), "samples_per_point": int(traj.shape[1])}
+            "inside_training_hull": round(inside, 4), "fallback_channels": int(fallback),
+            "samples_per_point": int(traj.shape[1]), **cost}
 
 
 def sweep_summary(sw: dict, steps: int) -> dict:
@@ -344,45 +356,25 @@ def sweep(args) -> int:
 
 
 def surrogate_gain(args) -> int:
-    import numpy as np
+    """The surrogate against the batched LBM on 64 fresh channels drawn like its training set."""
     import torch
     from paper_0807_0602_amd import surrogate as S
 
     steps = args.steps if args.steps != 10000 else 50_000
     every = 100
-    net = S.Network.load(args.weights)
-    wl = net.cfg.d_in == 5
     cases = S.draw_cases(64, seed=3, steps=steps, every=every)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     traj = S.simulate(cases, steps, every)
     torch.cuda.synchronize()
     lbm_s = time.perf_counter() - t0
-    errs, inside = S.curve_errors(net, cases, traj, wl)
-    X, T, w, k = S.dataset(cases, traj, wl)
-    net.predict(X)                       # warm-up
-    reps = 20
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        net.predict(X)
-    sur_s = (time.perf_counter() - t0) / reps
-    ok = np.isfinite(errs[:, 0])
-    within = float(np.mean(errs[ok, 0] <= 1.0))
-    lbm_pph = len(cases) * 3600.0 / lbm_s
-    sur_pph = len(cases) * 3600.0 / sur_s
+    sc = score_surrogate(args.weights, cases, traj, lbm_s)
     line = {
         "metric": "calibration-sweep points/hour: learned surrogate vs batched LBM (one point = one channel's z(t), p(t))",
-        "value": round(sur_pph, 1), "unit": "points/h", "n_gpus": 1, "steps": steps, "warmup": 1,
+        "value": sc["surrogate_points_per_hour"], "unit": "points/h", "n_gpus": 1, "steps": steps, "warmup": 1,
         "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "bf16 MFMA / f32 accumulate (network), f32 (LBM)", "data": "synthetic",
-        "config": {"workload": "surrogate_vs_lbm_64_channels", "inputs": int(net.cfg.d_in),
-                   "lbm_points_per_hour": round(lbm_pph, 1), "surrogate_points_per_hour": round(sur_pph, 1),
-                   "speedup": round(sur_pph / lbm_pph, 1), "scored_channels": int(ok.sum()),
-                   "max_dz_lu": float(np.nanmax(errs[:, 0])), "median_max_dz_lu": float(np.nanmedian(errs[:, 0])),
-                   "fraction_within_1lu": round(within, 4),
-                   "points_per_hour_within_1lu": round(sur_pph * within, 1),
-                   "inside_training_hull": round(inside, 4), "samples_per_point": int(traj.shape[1])},
+        "config": {"workload": "surrogate_vs_lbm_64_channels", **sc},
     }
     print(json.dumps(line), flush=True)
     return 0

@@ -278,12 +278,21 @@ def predict_curves(net: Network, cases: Sequence[Case], t: np.ndarray, with_leng
 #   python -m paper_0807_0602_amd.surrogate evaluate --weights w.npz --data heldout.npz
 # ---------------------------------------------------------------------------------------------
 
-def save_trajectories(path: str, cases: Sequence[Case], traj: np.ndarray, steps: int, every: int) -> None:
+def save_trajectories(path: str, cases: Sequence[Case], traj: np.ndarray, steps: int, every: int,
+                      seconds: float = float("nan")) -> None:
+    """Trajectories with their channel parameters and the GPU seconds the LBM took for them."""
     from .inputs import TAU_FOR_RATIO
     ratio_of = {tau: r for r, tau in TAU_FOR_RATIO.items()}
     meta = np.array([(c.geom.ny - 2, c.geom.x1 - c.geom.x0, c.params.gw[0], ratio_of[tuple(c.params.tau)], c.seed)
                      for c in cases], dtype=np.float64)
-    np.savez_compressed(path, meta=meta, traj=traj.astype(np.float32), steps=steps, every=every)
+    np.savez_compressed(path, meta=meta, traj=traj.astype(np.float32), steps=steps, every=every,
+                        seconds=float(seconds))
+
+
+def trajectory_seconds(path: str) -> float:
+    """The LBM seconds stored with a trajectory file (NaN if it has none)."""
+    z = np.load(path)
+    return float(z["seconds"]) if "seconds" in z.files else float("nan")
 
 
 def load_trajectories(path: str):
@@ -320,7 +329,7 @@ def _main(argv=None) -> int:
         t0 = time.perf_counter()
         traj = simulate(cases, a.steps, a.every, a.group, log=say)
         dt = time.perf_counter() - t0
-        save_trajectories(a.out, cases, traj, a.steps, a.every)
+        save_trajectories(a.out, cases, traj, a.steps, a.every, seconds=dt)
         unstable = int((traj[:, -1, 4] > 0).sum())
         say(json.dumps({"generated": a.n, "seconds": round(dt, 1), "unstable": unstable, "out": a.out}))
         return 0
@@ -344,8 +353,10 @@ def _main(argv=None) -> int:
             losses.append(net.train(min(chunk, a.steps - s0), a.batch))
             say(f"step {s0 + chunk}: minibatch loss {losses[-1]:.4f} (lattice units^2)")
         dt = time.perf_counter() - t0
+        data_s = sum(trajectory_seconds(p) for p in a.data)
         info = {"train_rows": int(X.shape[0]), "train_channels": len(cases), "steps": a.steps, "batch": a.batch,
-                "seconds": round(dt, 1), "final_loss": losses[-1]}
+                "seconds": round(dt, 1), "final_loss": losses[-1],
+                "data_seconds": round(data_s, 1) if math.isfinite(data_s) else None}
         if a.heldout:
             hc, ht = load_trajectories(a.heldout)
             errs, inside = curve_errors(net, hc, ht, wl)
