@@ -81,10 +81,10 @@ def kernel_hash(src: Optional[str] = None) -> str:
 def measured_traffic(cells: int, schedule: dict, path: Optional[str] = None, src: Optional[str] = None,
                      keys=("bx", "cy", "order", "fuse")):
     """HBM bytes per launch of a fused step from the committed counter summary for this
-    schedule (the 2-D capillary's file by default), or None if the kernel source changed since
-    the counters were taken."""
+    schedule (the 2-D capillary's file by default), or None if the kernel source (for the 2-D
+    capillary: the kernels and the runtime that plans their tiles) changed since the counters
+    were taken."""
     path = path or TRAFFIC_FILE
-    src = src or KERNEL_SRC
     try:
         with open(path) as f:
             t = json.load(f)
@@ -134,7 +134,7 @@ def summarize_counters(args) -> int:
         cells, workload = nx * ny * nz, "duct3d_%dx%dx%d" % (nx, ny, nz)
         sched = {"cy": min(args.cy3, ny)}
     else:
-        path, src, label = TRAFFIC_FILE, KERNEL_SRC, "k_step_fused / k_step_fused2"
+        path, src, label = TRAFFIC_FILE, None, "k_step_fused / k_step_fused2"
         from paper_0807_0602_amd import inputs
         case = inputs.capillary_roofline(seed=1)
         cells, workload = case.geom.nx * case.geom.ny, case.name

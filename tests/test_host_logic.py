@@ -104,6 +104,8 @@ def test_bench_counter_summary(tmp_path, monkeypatch):
     assert A.tile == (256, 16, 1, 1)
     assert bench.summarize_counters(A) == 0
     t = json.load(open(tmp_path / "traffic.json"))
+    # keyed by the kernels together with the runtime that plans their tiles
+    assert t["kernel_sha256_16"] == bench.kernel_hash() != bench.kernel_hash(bench.KERNEL_SRC)
     e = t["schedules"][0]
     assert e["fetch_scale"] == 2.0 and e["write_scale"] == 1.0
     assert e["read_bytes_per_launch"] == 600000 * 2 * 1024 and e["write_bytes_per_launch"] == 1179000 * 1024
