@@ -183,9 +183,11 @@ def test_drag_corrected_front_law(scf, tau):
 def test_complete_wetting_precursor_grows(scf):
     """The paper's H = 40 capillary (1200 x 42, capillary x in [300, 1100)), tau = (1, 1).  At
     G_w = -+0.6 (complete wetting) the film leads the centre-line front, p >= z, and the lead
-    grows as a power of time with an exponent between 0 and 1; at G_w = -+0.3 (partial wetting,
-    cos(theta) 0.67) it stays constant.  The GPU run is checked against the FP64 oracle over its
-    first 1000 steps at the strong coupling."""
+    grows sub-linearly: as a power of time with an exponent between 0 and 1, its growth slowing
+    (a line in sqrt(t) fits it better than a line in t; measured R^2 0.93 against 0.84, and 0.99
+    for a line in log t: slower than the paper's sqrt(t) at these couplings); at G_w = -+0.3
+    (partial wetting, cos(theta) 0.67) it stays constant.  The GPU run is checked against the
+    FP64 oracle over its first 1000 steps at the strong coupling."""
     geom = inputs.Geometry(1200, 42, 300, 1100)
     cases = [inputs.Case(geom, inputs.Params(G=0.9, gw=gw), seed=3, liquid_x1=300)
              for gw in ((-0.6, 0.6), (-0.3, 0.3))]
@@ -225,6 +227,16 @@ def test_complete_wetting_precursor_grows(scf):
     assert np.all(lead > 5.0)
     assert lead[-1] - lead[0] >= 5.0
     assert 0.05 < beta < 1.0
+
+    def r2(x):
+        c = np.polyfit(x, lead, 1)
+        return 1.0 - np.sum((lead - np.polyval(c, x)) ** 2) / np.sum((lead - lead.mean()) ** 2)
+
+    h = len(t) // 2
+    _say(f"  lead against sqrt(t): R^2 {r2(np.sqrt(t)):.3f}, against t: {r2(t):.3f}, against log t: "
+         f"{r2(np.log(t)):.3f}")
+    assert r2(np.sqrt(t)) > r2(t)
+    assert (lead[-1] - lead[h]) / (t[-1] - t[h]) < (lead[h] - lead[0]) / (t[h] - t[0])
     t, lead = out[1]
     assert np.all(lead > 0.0)
     assert abs(_lead_exponent(t, lead)) < 0.03
