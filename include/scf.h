@@ -53,7 +53,10 @@ enum {
 };
 
 typedef struct {
-    int32_t nx, ny;    /* box size, nx >= 3, ny >= 3, nx < 2^20, ny < 2^20 */
+    int32_t nx, ny;    /* box size, nx >= 3, ny >= 3, nx < 2^20, ny < 2^20, and one population
+                          buffer (18 planes of ny rows of nx rounded up to 64 FP32 values) below
+                          2 GiB, about 29.8 M nodes per channel (the fused kernels address a
+                          buffer with 32-bit byte offsets); larger problems are several channels */
     int32_t x0, x1;    /* solid rows y = 0 and y = ny-1 for x in [x0, x1); x0 == x1: no walls */
     const uint8_t* solid;  /* optional host mask, ny*nx bytes row-major, non-zero = solid node.
                               When given it REPLACES the wall rows as the set of solid nodes
@@ -124,7 +127,8 @@ typedef struct scf_batch scf_batch;
 
 /* Device workspace needed for one channel: two FP32 population buffers (2 x 2 x 9 planes),
  * a 2-plane density field, per-row partial sums and one observation record; each plane is
- * ny rows of nx rounded up to 64 floats.  0 if the geometry is invalid. */
+ * ny rows of nx rounded up to 64 floats.  0 if the geometry is invalid (including a channel
+ * above the 2 GiB population-buffer limit of scf_geometry). */
 size_t scf_workspace_bytes(const scf_geometry* geom);
 
 /* Create a context and set every population to the rest equilibrium of eqs. feq1-feq3,
