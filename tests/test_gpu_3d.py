@@ -221,3 +221,34 @@ def test_full_size_duct_fused_equals_two_kernel(S):
         del ch
         torch.cuda.empty_cache()
     assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
+
+
+def test_largest_box_fused_equals_two_kernel(S):
+    """The largest 3-D box the fused step takes: one component's 19 planes just below 2 GiB
+    (512 x 236 x 232, 28.0 M nodes), where the fused kernel forms its largest 32-bit byte offsets.
+    Its densities after 6 steps equal the two-kernel step's (64-bit indexing) bit for bit, with
+    mass conserved and no flag."""
+    import torch
+    nx, ny, nz, x0, x1 = 512, 236, 232, 128, 384
+    Z, Y, X = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    liq = X < x0
+    a = np.where(liq, 2.0, 0.06) + 1e-3 * inputs.uniform_pm1(2, 0, Y * nz + Z, X)
+    b = np.where(liq, 0.06, 2.0) + 1e-3 * inputs.uniform_pm1(2, 1, Y * nz + Z, X)
+    del Z, Y, X, liq
+    prm = inputs.Params(G=0.9, gw=(-0.2, 0.2))
+    _say("case: largest 3-D box 512x236x232, fused vs two-kernel, 6 steps")
+    out = []
+    for fused in (True, False):
+        ch = S.Channel3(nx, ny, nz, x0, x1, prm, a, b, walls_y=True, walls_z=True)
+        ch.set_schedule(fused=fused, cy=16)
+        assert ch.schedule()["fused"] == fused
+        m0 = ch.observe()["mass"]
+        ch.step(6)
+        o = ch.observe()
+        assert o["flags"] == 0
+        for k in range(2):
+            assert abs(o["mass"][k] - m0[k]) / m0[k] < 1e-5
+        out.append(ch.density())
+        del ch
+        torch.cuda.empty_cache()
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])

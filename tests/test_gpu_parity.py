@@ -380,3 +380,33 @@ def test_full_size_roofline_case_mass_and_observables(scf):
     for k in range(2):
         assert abs(o1["mass"][k] - o0["mass"][k]) / o0["mass"][k] < 1e-5
     assert o1["flags"] == 0
+
+
+def test_largest_channel_bitwise(scf):
+    """The largest channel one context takes: one population buffer just below 2 GiB (16384 x
+    1820, 29.8 M nodes), where the fused kernels form their largest 32-bit byte offsets.  The
+    default two-step schedule and the two-kernel step (64-bit indexing) give the same densities
+    bit for bit after 6 steps, with mass conserved and no flag."""
+    import torch
+    from paper_0807_0602_amd import _lib as L
+    geom = inputs.Geometry(16384, 1820, 4096, 12288)
+    case = inputs.Case(geom, inputs.Params(G=0.9, gw=(-0.2, 0.2)), seed=4, liquid_x1=4096)
+    _say("case: largest channel 16384x1820, two-step default vs two-kernel, 6 steps")
+    out = []
+    for two_kernel in (False, True):
+        ch = scf.Channel.from_case(case)
+        if two_kernel:
+            ch.set_variant(L.SCF_VARIANT_TWO_KERNEL)
+        else:
+            ch.set_tile(**BENCH_TILE)
+        m0 = ch.observe()["mass"]
+        ch.step(6)
+        o = ch.observe()
+        assert o["flags"] == 0
+        for k in range(2):
+            assert abs(o["mass"][k] - m0[k]) / m0[k] < 1e-5
+        out.append(ch.density())
+        ch.close()
+        del ch
+        torch.cuda.empty_cache()
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
