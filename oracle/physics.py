@@ -35,7 +35,3 @@ def droplet_radius(nA, level_in: float, level_out: float) -> float:
     frac = (np.asarray(nA) - level_out) / (level_in - level_out)
     return float(np.sqrt(frac.sum() / np.pi))
 
-
-def phase_viscosity(n_major: float, n_minor: float, tau_major: float, tau_minor: float) -> float:
-    """mu = sum_k rho_k nu_k of one bulk phase."""
-    return n_major * kinematic_viscosity(tau_major) + n_minor * kinematic_viscosity(tau_minor)

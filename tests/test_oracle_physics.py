@@ -123,6 +123,18 @@ def test_unequal_masses_flat_interface():
     assert np.abs(u).max() <= 1e-6
 
 
+def test_droplet_radius_of_a_synthetic_drop():
+    """The drop-radius read-out used by the Laplace pin: a disc of radius R with a smooth
+    (tanh, width 1.5) interface between the liquid and gas levels has the area of a circle of
+    radius R up to O(width^2 / R), wherever its centre sits on the grid."""
+    n = 96
+    Y, X = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    for R, cx, cy in ((10.0, 47.5, 47.5), (15.3, 40.2, 51.7), (26.0, 48.0, 46.3)):
+        r = np.hypot(X - cx, Y - cy)
+        nA = 0.06 + (2.0 - 0.06) * 0.5 * (1.0 - np.tanh((r - R) / 1.5))
+        assert abs(physics.droplet_radius(nA, 2.0, 0.06) - R) < 0.1
+
+
 def test_laplace_law():
     n = 96
     rows = []
