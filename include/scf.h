@@ -54,9 +54,10 @@ enum {
 
 typedef struct {
     int32_t nx, ny;    /* box size, nx >= 3, ny >= 3, nx < 2^20, ny < 2^20, and one population
-                          buffer (18 planes of ny rows of nx rounded up to 64 FP32 values) below
-                          2 GiB, about 29.8 M nodes per channel (the fused kernels address a
-                          buffer with 32-bit byte offsets); larger problems are several channels */
+                          buffer (18 planes of ny rows of nx rounded up to 64 FP32 values) at
+                          most 4 GiB, about 59.6 M nodes per channel (the fused kernels address a
+                          buffer with unsigned 32-bit byte offsets); larger problems are several
+                          channels */
     int32_t x0, x1;    /* solid rows y = 0 and y = ny-1 for x in [x0, x1); x0 == x1: no walls */
     const uint8_t* solid;  /* optional host mask, ny*nx bytes row-major, non-zero = solid node.
                               When given it REPLACES the wall rows as the set of solid nodes
@@ -128,7 +129,7 @@ typedef struct scf_batch scf_batch;
 /* Device workspace needed for one channel: two FP32 population buffers (2 x 2 x 9 planes),
  * a 2-plane density field, per-row partial sums and one observation record; each plane is
  * ny rows of nx rounded up to 64 floats.  0 if the geometry is invalid (including a channel
- * above the 2 GiB population-buffer limit of scf_geometry). */
+ * above the 4 GiB population-buffer limit of scf_geometry). */
 size_t scf_workspace_bytes(const scf_geometry* geom);
 
 /* Create a context and set every population to the rest equilibrium of eqs. feq1-feq3,
@@ -337,7 +338,8 @@ void scf_sur_destroy(scf_sur* s);
  * 2-D model.  FP32 state.  By default one fused kernel per step: tiles of 64 x 4 (x, z) nodes walk
  * cy rows of y, keeping the densities of three y-slices in LDS; the two-kernel form (a density
  * field, then pull + collide) is selectable (scf3_set_schedule) and is the only one when one
- * component's 19 planes exceed 2 GiB (32-bit buffer offsets).  Both give identical results.
+ * component's 19 planes exceed 4 GiB (unsigned 32-bit buffer offsets).  Both give identical
+ * results.
  * ------------------------------------------------------------------------------------------- */
 
 typedef struct {
@@ -380,7 +382,7 @@ int scf3_step(scf3_ctx* ctx, int64_t nsteps);
  * form where the fused one does not fit) or fused = 0 (two kernels, cy ignored).  The state is
  * unchanged; results do not depend on the schedule.  *_get_* writes the current one.
  * Errors: SCF_EINVAL (fused not 0/1, cy < 1, or fused = 1 where a component's 19 planes exceed
- * 2 GiB). */
+ * 4 GiB). */
 int scf3_set_schedule(scf3_ctx* ctx, int32_t fused, int32_t cy);
 int scf3_get_schedule(const scf3_ctx* ctx, int32_t* fused, int32_t* cy);
 

@@ -176,10 +176,10 @@ __device__ __forceinline__ bool near_solid(const Chan3& c, int x, int y, int z) 
 }
 
 // Buffer-descriptor access for the fused step: one descriptor per component of the source buffer
-// (19 planes, below 2 GiB, checked by the host), 32-bit byte offsets, plane offsets in scalar
-// registers.
+// (19 planes, at most 4 GiB, checked by the host), unsigned 32-bit byte offsets, plane offsets in
+// scalar registers.
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const float* base, int64_t bytes) {
-    return __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(base), 0, (int)bytes, 0x00020000);
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(base), 0, (int)(uint32_t)bytes, 0x00020000);
 }
 __device__ __forceinline__ float bload(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
     return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0));

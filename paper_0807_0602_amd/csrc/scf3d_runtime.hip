@@ -42,8 +42,8 @@ bool geom_ok(const scf3_geometry* g, std::string* why) {
 
 int pitch_of(int nx) { return (nx + 63) / 64 * 64; }
 
-// The fused kernel addresses one component's 19 planes with 32-bit buffer offsets.
-bool fused_fits(int64_t plane) { return (int64_t)19 * plane * (int64_t)sizeof(float) <= INT32_MAX; }
+// The fused kernel addresses one component's 19 planes with unsigned 32-bit buffer offsets.
+bool fused_fits(int64_t plane) { return (int64_t)19 * plane * (int64_t)sizeof(float) <= (int64_t)UINT32_MAX; }
 
 Plan3 plan(const scf3_geometry& g) {
     Plan3 p;
@@ -160,7 +160,7 @@ int scf3_set_schedule(scf3_ctx* c, int32_t fused, int32_t cy) {
     if (fused != 0 && fused != 1) return fail(SCF_EINVAL, "fused must be 0 or 1");
     if (fused && cy < 1) return fail(SCF_EINVAL, "cy must be >= 1");
     if (fused && !fused_fits(c->chan.plane))
-        return fail(SCF_EINVAL, "box too large for the fused kernel (19 planes above 2 GiB)");
+        return fail(SCF_EINVAL, "box too large for the fused kernel (19 planes above 4 GiB)");
     c->fused = fused;
     if (fused) c->cy = cy;
     return SCF_OK;

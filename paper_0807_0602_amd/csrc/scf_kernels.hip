@@ -106,16 +106,17 @@ __device__ __forceinline__ uint32_t pull_node(const float* __restrict__ g, const
 // at most 4 GiB, checked by the host), 32-bit byte offsets, plane offsets in scalar registers.
 constexpr int kBufferDword3 = 0x00020000;   // raw buffer, 32-bit data format (gfx9 family)
 
+// Byte counts and offsets are unsigned 32-bit values (the builtins take them as int bit patterns).
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const float* base, int64_t bytes) {
-    return __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(base), 0, (int)bytes, kBufferDword3);
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(base), 0, (int)(uint32_t)bytes, kBufferDword3);
 }
-__device__ __forceinline__ float bload(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+__device__ __forceinline__ float bload(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0));
 }
 
 // As pull18, through a buffer descriptor; Pb = plane size in bytes.
 template <bool WALLS>
-__device__ __forceinline__ void pull18_buf(__amdgpu_buffer_rsrc_t r, int Pb, const Chan& c, int x,
+__device__ __forceinline__ void pull18_buf(__amdgpu_buffer_rsrc_t r, uint32_t Pb, const Chan& c, int x,
                                            int y, uint32_t code, float f[18]) {
     const int xm = dec_wrap(x, c.nx), xp = inc_wrap(x, c.nx);
     const int ym = dec_wrap(y, c.ny), yp = inc_wrap(y, c.ny);
@@ -124,17 +125,18 @@ __device__ __forceinline__ void pull18_buf(__amdgpu_buffer_rsrc_t r, int Pb, con
     const int opp[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
-        const int off = (sy[i] * c.pitch + sx[i]) * 4;
+        const uint32_t off = ((uint32_t)sy[i] * (uint32_t)c.pitch + (uint32_t)sx[i]) * 4u;
         if (WALLS && i > 0) {
             // bounce-back lanes read their own node's opposite direction: fold the plane into
             // the per-lane offset so the scalar offset stays uniform
             const bool sol = (code >> opp[i]) & 1u;
-            const int o = sol ? (y * c.pitch + x) * 4 + opp[i] * Pb : off + i * Pb;
-            f[i] = bload(r, o, 0);
-            f[9 + i] = bload(r, o, 9 * Pb);
+            const uint32_t o = sol ? ((uint32_t)y * (uint32_t)c.pitch + (uint32_t)x) * 4u + (uint32_t)opp[i] * Pb
+                                   : off + (uint32_t)i * Pb;
+            f[i] = bload(r, o, 0u);
+            f[9 + i] = bload(r, o, 9u * Pb);
         } else {
-            f[i] = bload(r, off, i * Pb);
-            f[9 + i] = bload(r, off, (9 + i) * Pb);
+            f[i] = bload(r, off, (uint32_t)i * Pb);
+            f[9 + i] = bload(r, off, (uint32_t)(9 + i) * Pb);
         }
     }
 }
@@ -142,7 +144,7 @@ __device__ __forceinline__ void pull18_buf(__amdgpu_buffer_rsrc_t r, int Pb, con
 // Pull for the fused step; returns the node's solid-neighbourhood code.  MASK instantiates the
 // masked-channel path (a code load per node); row-walled channels test their rows instead.
 template <bool MASK>
-__device__ __forceinline__ uint32_t pull_node_buf(__amdgpu_buffer_rsrc_t r, int Pb, const Chan& c,
+__device__ __forceinline__ uint32_t pull_node_buf(__amdgpu_buffer_rsrc_t r, uint32_t Pb, const Chan& c,
                                                   const float* ws, int x, int y, float f[18]) {
     if (MASK && c.masked) {
         const uint32_t code = mask_code(c, ws, x, y);
@@ -174,10 +176,11 @@ struct GlobalOut {
 template <int AUX>   // 2: non-temporal, 0: cached
 struct BufferOutT {
     __amdgpu_buffer_rsrc_t r;
-    int Pb;
-    int off;
+    uint32_t Pb;
+    uint32_t off;
     __device__ __forceinline__ void operator()(int q, float v) const {
-        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, off, q * Pb, AUX);
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)off,
+                                              (int)((uint32_t)q * Pb), AUX);
     }
 };
 using BufferOut = BufferOutT<2>;
@@ -303,7 +306,7 @@ k_step_fused(const Chan* __restrict__ chans, const TileDesc* __restrict__ tiles,
         const int64_t buf_bytes = (int64_t)18 * c.plane * 4;
         const __amdgpu_buffer_rsrc_t rs = make_rsrc(ws + c.off + (int64_t)src * 18 * c.plane, buf_bytes);
         const __amdgpu_buffer_rsrc_t rd = make_rsrc(ws + c.off + (int64_t)(src ^ 1) * 18 * c.plane, buf_bytes);
-        const int Pb = (int)(c.plane * 4);
+        const uint32_t Pb = (uint32_t)(c.plane * 4);
         const int hx = tid == 0 ? (td.xb == 0 ? c.nx - 1 : td.xb - 1)
                                 : (td.xb + w == c.nx ? 0 : td.xb + w);
         const int hslot = tid == 0 ? 0 : w + 1;
@@ -363,7 +366,7 @@ k_step_fused(const Chan* __restrict__ chans, const TileDesc* __restrict__ tiles,
                     float swx = 0.0f, swy = 0.0f;
                     if (qcode) wall_sum(qcode, swx, swy);
                     collide_store(c, q, qA, qB, sAx, sAy, sBx, sBy, swx, swy,
-                                  BufferOut{rd, Pb, (yc * c.pitch + x) * 4});
+                                  BufferOut{rd, Pb, ((uint32_t)yc * (uint32_t)c.pitch + (uint32_t)x) * 4u});
                 }
             }
 #pragma unroll
@@ -458,7 +461,7 @@ k_step_fused2(const Chan* __restrict__ chans, const TileDesc* __restrict__ tiles
         const int64_t buf_bytes = (int64_t)18 * c.plane * 4;
         const __amdgpu_buffer_rsrc_t rs = make_rsrc(ws + c.off + (int64_t)src * 18 * c.plane, buf_bytes);
         const __amdgpu_buffer_rsrc_t rd = make_rsrc(ws + c.off + (int64_t)(src ^ 1) * 18 * c.plane, buf_bytes);
-        const int Pb = (int)(c.plane * 4);
+        const uint32_t Pb = (uint32_t)(c.plane * 4);
         // stage 1: densities and code of the pulled row awaiting collision (its populations wait
         // in sq)
         float qA = 0.0f, qB = 0.0f;
@@ -610,7 +613,7 @@ k_step_fused2(const Chan* __restrict__ chans, const TileDesc* __restrict__ tiles
                 float swx = 0.0f, swy = 0.0f;
                 if (q2code) wall_sum(q2code, swx, swy);
                 collide_store(c, q2, q2A, q2B, sAx, sAy, sBx, sBy, swx, swy,
-                              BufferOutCached{rd, Pb, (yc * c.pitch + x) * 4});
+                              BufferOutCached{rd, Pb, ((uint32_t)yc * (uint32_t)c.pitch + (uint32_t)x) * 4u});
             }
 #pragma unroll
             for (int m = 0; m < 2; ++m) {

@@ -74,9 +74,9 @@ bool geom_ok(const scf_geometry* g, std::string* why) {
         *why = "need 0 <= x0 <= x1 <= nx";
         return false;
     }
-    // one population buffer (18 planes of FP32) is addressed with 32-bit byte offsets
-    if ((int64_t)18 * 4 * g->ny * pitch_of(g->nx) >= (int64_t)std::numeric_limits<int32_t>::max()) {
-        *why = "ny * nx too large for one channel (18 planes must stay below 2 GiB)";
+    // one population buffer (18 planes of FP32) is addressed with unsigned 32-bit byte offsets
+    if ((int64_t)18 * 4 * g->ny * pitch_of(g->nx) > (int64_t)std::numeric_limits<uint32_t>::max()) {
+        *why = "ny * nx too large for one channel (18 planes must stay below 4 GiB)";
         return false;
     }
     return true;

@@ -37,9 +37,9 @@ def test_workspace_sizes_and_validation():
     assert n >= 38 * 24 * pitch * 4
     assert L.scf_workspace_bytes(C.byref(L.scf_geometry(2, 24, 0, 0))) == 0      # nx too small
     assert L.scf_workspace_bytes(C.byref(L.scf_geometry(200, 24, 150, 50))) == 0  # x1 < x0
-    # one population buffer (18 FP32 planes) must stay below 2 GiB: 16384 x 1820 fits, x 1821 not
-    assert L.scf_workspace_bytes(C.byref(L.scf_geometry(16384, 1820, 4096, 12288))) > 2 * 18 * 4 * 1820 * 16384
-    assert L.scf_workspace_bytes(C.byref(L.scf_geometry(16384, 1821, 4096, 12288))) == 0
+    # one population buffer (18 FP32 planes) must stay within 4 GiB: 16384 x 3640 fits, x 3641 not
+    assert L.scf_workspace_bytes(C.byref(L.scf_geometry(16384, 3640, 4096, 12288))) > 2 * 18 * 4 * 3640 * 16384
+    assert L.scf_workspace_bytes(C.byref(L.scf_geometry(16384, 3641, 4096, 12288))) == 0
     gs = (L.scf_geometry * 2)(L.scf_geometry(200, 24, 50, 150), L.scf_geometry(96, 22, 24, 72))
     assert L.scf_batch_workspace_bytes(2, gs, 10) > n
 

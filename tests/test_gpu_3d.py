@@ -224,19 +224,20 @@ def test_full_size_duct_fused_equals_two_kernel(S):
 
 
 def test_largest_box_fused_equals_two_kernel(S):
-    """The largest 3-D box the fused step takes: one component's 19 planes just below 2 GiB
-    (512 x 236 x 232, 28.0 M nodes), where the fused kernel forms its largest 32-bit byte offsets.
+    """The largest 3-D box the fused step takes: one component's 19 planes just within 4 GiB
+    (512 x 332 x 332, 56.4 M nodes), where the fused kernel forms its largest unsigned 32-bit byte
+    offsets (above 2^31).
     Its densities after 6 steps equal the two-kernel step's (64-bit indexing) bit for bit, with
     mass conserved and no flag."""
     import torch
-    nx, ny, nz, x0, x1 = 512, 236, 232, 128, 384
+    nx, ny, nz, x0, x1 = 512, 332, 332, 128, 384
     Z, Y, X = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
     liq = X < x0
     a = np.where(liq, 2.0, 0.06) + 1e-3 * inputs.uniform_pm1(2, 0, Y * nz + Z, X)
     b = np.where(liq, 0.06, 2.0) + 1e-3 * inputs.uniform_pm1(2, 1, Y * nz + Z, X)
     del Z, Y, X, liq
     prm = inputs.Params(G=0.9, gw=(-0.2, 0.2))
-    _say("case: largest 3-D box 512x236x232, fused vs two-kernel, 6 steps")
+    _say("case: largest 3-D box 512x332x332, fused vs two-kernel, 6 steps")
     out = []
     for fused in (True, False):
         ch = S.Channel3(nx, ny, nz, x0, x1, prm, a, b, walls_y=True, walls_z=True)

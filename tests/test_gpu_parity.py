@@ -383,15 +383,15 @@ def test_full_size_roofline_case_mass_and_observables(scf):
 
 
 def test_largest_channel_bitwise(scf):
-    """The largest channel one context takes: one population buffer just below 2 GiB (16384 x
-    1820, 29.8 M nodes), where the fused kernels form their largest 32-bit byte offsets.  The
-    default two-step schedule and the two-kernel step (64-bit indexing) give the same densities
-    bit for bit after 6 steps, with mass conserved and no flag."""
+    """The largest channel one context takes: one population buffer just within 4 GiB (16384 x
+    3640, 59.6 M nodes), where the fused kernels form their largest unsigned 32-bit byte offsets
+    (above 2^31).  The default two-step schedule and the two-kernel step (64-bit indexing) give
+    the same densities bit for bit after 6 steps, with mass conserved and no flag."""
     import torch
     from paper_0807_0602_amd import _lib as L
-    geom = inputs.Geometry(16384, 1820, 4096, 12288)
+    geom = inputs.Geometry(16384, 3640, 4096, 12288)
     case = inputs.Case(geom, inputs.Params(G=0.9, gw=(-0.2, 0.2)), seed=4, liquid_x1=4096)
-    _say("case: largest channel 16384x1820, two-step default vs two-kernel, 6 steps")
+    _say("case: largest channel 16384x3640, two-step default vs two-kernel, 6 steps")
     out = []
     for two_kernel in (False, True):
         ch = scf.Channel.from_case(case)
