@@ -157,13 +157,12 @@ def test_drag_corrected_front_law(scf, tau):
     else:
         # unequal relaxation times: the realised ratio, Poiseuille's law in the gas column within
         # the scatter of its pressure gradient (sound waves, +-20 % between snapshots), and the
-        # front law's linearity are pinned; the slope is reported against the prediction (0.76
-        # with sum_k rho_k nu_k, 0.85 with the gas column's measured viscosity, which is 13 %
-        # higher: the mixture with unequal tau dissipates more than sum_k rho_k nu_k says) and
-        # held only above 0.7
+        # front law's linearity are pinned; the slope is held against the prediction with the gas
+        # column's measured viscosity (measured 0.85; 0.76 with sum_k rho_k nu_k: the gas column
+        # dissipates 13 % more than sum_k rho_k nu_k says when the relaxation times differ)
         assert mu_l / mu_g > 2.0 and mu_l_eff / mu_g_eff > 1.8
         assert abs(mu_g_eff / mu_g - 1.0) < 0.25
-        assert 0.7 <= slope / pred <= 1.15
+        assert 0.8 <= slope / pred <= 1.15
     # partial wetting: the wall-row film (n_A above a third of the reservoir's bulk value, read at
     # the reservoir centre x0/2) leads the centre-line front by a distance that does not grow while that
     # reading is bulk liquid; the channel draws the reservoir's far interface towards its centre,
